@@ -1,0 +1,223 @@
+#!/usr/bin/env python
+"""Benchmark of the ILS hot path on one MI355X.
+
+A step is one full ILS smoothing (Algorithm 1, N = 4 iterations:
+2N + 1 = 9 fused passes) of one 1920 x 1080 RGB float32 frame
+(lambda = 1, p = 0.8, eps = 1e-4), the frames taken in turn from a ring of
+distinct seeded synthetic frames that are resident in HBM before timing
+starts (the ring is larger than the 256 MB last-level cache).
+
+Prints one JSON line with throughput (Mpixel/s, an RGB pixel counted once),
+fps, the roofline of the dominant kernel (per-launch durations from HIP
+events on the library's stream, algorithmic bytes per launch), the FP64
+oracle timed on the host cores, and secondary figures (hot single frame,
+batched frames).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mpixel/s and fps at 1080p RGB N=4 (FP32 ILS vs surrogate), HBM GB/s % peak"
+HBM_PEAK_GBS = 8000.0
+PAPER_1080P_RGB_MPX_S = 1920 * 1080 * 20 / 1e6  # 20 fps on a GTX 1080 (paper's GPU timing table)
+
+
+def pass_bytes(H, W, C):
+    """Algorithmic HBM bytes of each pass kind for one frame (all channels)."""
+    img = C * H * W * 4
+    spec = C * H * (W // 2 + 1) * 8
+    return {"row_first": img + spec, "row_mid": img + 2 * spec, "row_final": spec + img, "column": 2 * spec}
+
+
+def step_bytes(H, W, C, N):
+    b = pass_bytes(H, W, C)
+    return b["row_first"] + (N - 1) * b["row_mid"] + N * b["column"] + b["row_final"]
+
+
+def source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2003_07504_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".hpp", ".cpp", ".def")):
+            with open(os.path.join(csrc, name), "rb") as fh:
+                h.update(name.encode())
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel, H, W, C):
+    """HBM bytes per launch measured with rocprofv3 counters (committed under
+    profiles/), or None when absent or taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    e = t.get(f"{kernel}@{H}x{W}x{C}")
+    if not e or e.get("source_hash") != source_hash():
+        return None
+    return e["bytes_per_launch"]
+
+
+def cpu_baseline(frames_np, H, W, C, lam, p, eps, N, seconds):
+    from oracle.ils import ils_channels
+    workers = min(16, os.cpu_count() or 1)
+    t0 = time.perf_counter()
+    done = 0
+    while True:
+        ils_channels(frames_np[done % len(frames_np)].astype("float64"), lam, p, eps, N, workers=workers)
+        done += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    el = time.perf_counter() - t0
+    return {"value": round(done * H * W / el / 1e6, 4), "unit": "Mpixel/s", "cores": workers, "kind": "oracle",
+            "sample": f"{done} frame(s) of {W}x{H}x{C}, N={N}, FP64 NumPy/SciPy oracle (scipy.fft workers={workers})",
+            "fps": round(done / el, 4)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=256)
+    ap.add_argument("--warmup", type=int, default=32)
+    ap.add_argument("--ring", type=int, default=16, help="distinct frames cycled through")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the hot-frame and batched figures")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: --gpus {args.gpus} is not supported: this build runs on one GPU only "
+              "(frames would shard across GPUs with no exchange; see the design notes).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2003_07504_amd import ils
+    from synth import voronoi_image
+
+    H, W, C, lam, p, eps, N = 1080, 1920, 3, 1.0, 0.8, 1e-4, 4
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    frames_np = [voronoi_image(H, W, C, 400, 0.05, seed=1 + i) for i in range(args.ring)]
+    ring = [torch.from_numpy(f).to(dev) for f in frames_np]
+    outs = [torch.empty_like(f) for f in ring]
+    plan = ils.Plan(H, W, C, max_frames=8)
+    torch.cuda.synchronize()
+
+    def run(k0, k):
+        for i in range(k0, k0 + k):
+            j = i % len(ring)
+            plan.smooth(ring[j], lam, p, eps, N, out=outs[j])
+
+    run(0, args.warmup)
+    torch.cuda.synchronize()
+    # ---- timed region
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    run(args.warmup, args.steps)
+    ev1.record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    host_s = t1 - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    if plan.last_error() != 0:
+        raise RuntimeError("HIP error during the timed region")
+    elapsed = max(host_s, gpu_ms / 1e3)
+    ms_per_step = elapsed * 1e3 / args.steps
+    mpx = args.steps * H * W / elapsed / 1e6
+    fps = args.steps / elapsed
+
+    # ---- per-pass durations (HIP events around every launch, same workload)
+    plan.profile_begin()
+    run(args.warmup + args.steps, args.steps)
+    prof = plan.profile_end()
+    torch.cuda.synchronize()
+    pb = pass_bytes(H, W, C)
+    per_kind = {k: {"avg_us": round(1e3 * t / n, 3), "launches": n, "alg_bytes": pb[k],
+                    "alg_GBs": round(pb[k] / (t / n * 1e-3) / 1e9, 1)}
+                for k, (t, n) in prof.items() if n > 0}
+    dom = max(per_kind, key=lambda k: per_kind[k]["avg_us"] * per_kind[k]["launches"])
+    dk = per_kind[dom]
+    achieved = dk["alg_GBs"]
+    traffic = traffic_from_profiles(dom, H, W, C)
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
+                "avg_launch_us": dk["avg_us"], "alg_bytes_per_launch": dk["alg_bytes"]}
+    step_alg = step_bytes(H, W, C, N)
+
+    extras = {}
+    if not args.no_extras:
+        # hot: the same frame over and over (working set resident in the last-level cache)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(args.steps):
+            plan.smooth(ring[0], lam, p, eps, N, out=outs[0])
+        torch.cuda.synchronize()
+        hot = (time.perf_counter() - a) / args.steps
+        extras["hot_single_frame"] = {"ms_per_frame": round(hot * 1e3, 4), "fps": round(1 / hot, 1),
+                                      "Mpixel_s": round(H * W / hot / 1e6, 1)}
+        # batched: 8 frames per ils_smooth_batch call
+        nb = 8
+        batches = max(1, args.steps // nb)
+        frames = [(ring[j], lam, p, eps, N) for j in range(nb)]
+        for _ in range(2):
+            plan.smooth_batch(frames, outs=outs[:nb])
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for bi in range(batches):
+            off = (bi * nb) % len(ring)
+            idx = [(off + j) % len(ring) for j in range(nb)]
+            plan.smooth_batch([(ring[j], lam, p, eps, N) for j in idx], outs=[outs[j] for j in idx])
+        torch.cuda.synchronize()
+        bt = (time.perf_counter() - a) / (batches * nb)
+        extras["batched_8_frames"] = {"ms_per_frame": round(bt * 1e3, 4), "fps": round(1 / bt, 1),
+                                      "Mpixel_s": round(H * W / bt / 1e6, 1)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(frames_np, H, W, C, lam, p, eps, N, args.cpu_seconds)
+
+    line = {
+        "metric": METRIC,
+        "value": round(mpx, 2),
+        "unit": "Mpixel/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": round(mpx / PAPER_1080P_RGB_MPX_S, 2),
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "ILS 1920x1080 RGB float32, N=4, lambda=1, p=0.8, eps=1e-4, "
+                               f"one frame per step from a ring of {args.ring} distinct Voronoi+Gaussian frames",
+                   "H": H, "W": W, "C": C, "N": N, "lambda": lam, "p": p, "eps": eps,
+                   "global_batch": 1, "parallelism": "none (1 GPU)"},
+        "fps": round(fps, 1),
+        "alg_GBs_whole_step": round(step_alg / (ms_per_step * 1e-3) / 1e9, 1),
+        "alg_bytes_per_step": step_alg,
+        "host_s": round(host_s, 6),
+        "gpu_event_ms": round(gpu_ms, 4),
+        "roofline": roofline,
+        "passes": per_kind,
+        "cpu_baseline": cpu,
+        "extras": extras,
+    }
+    plan.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

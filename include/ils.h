@@ -1,0 +1,161 @@
+/*
+ * ils.h -- C ABI of the MI355X (gfx950) library for Iterative Least Squares
+ * edge-preserving smoothing (Liu, Zhang, Huang, Yang, Shen, Reid: "Real-time
+ * Image Smoothing via Iterative Least Squares").
+ *
+ * The library runs Algorithm 1 of the paper: starting from u^0 = f it
+ * repeats N times
+ *     mu^n = c nabla u^n - phi_p'(nabla u^n)                       Eq. (7)
+ *     u^{n+1} = argmin_u sum (u - f)^2
+ *               + lambda/2 sum (sqrt(c) nabla u - mu^n / sqrt(c))^2  Eq. (8)
+ * with phi_p(x) = (x^2 + eps)^(p/2) (Eq. (2)), c = c0 = p eps^(p/2 - 1)
+ * (Eq. (11), Sec. 3.3.3), nabla = periodic forward differences along x and
+ * y (the [1, -1] kernels of Sec. 3), and the LS problem solved in the
+ * Fourier domain under periodic boundaries (Eq. (9), Sec. 3.2) with one
+ * real 2-D FFT and one inverse per iteration.  Colour images are smoothed
+ * channel by channel (Sec. 3.4).  Arithmetic is float32.
+ *
+ * Conventions for every entry point:
+ *   - Images are planar float32, C x H x W, row-major, contiguous, channel
+ *     stride H*W.  Image pointers are DEVICE pointers owned by the caller.
+ *   - Work is enqueued on the plan's HIP stream and the call returns after
+ *     enqueue (asynchronous).  The caller synchronises the stream.
+ *   - Every argument is validated before anything is enqueued; a non-zero
+ *     status means nothing was enqueued.  Asynchronous HIP failures are
+ *     reported by ils_last_error() after the stream has been synchronised.
+ *   - The library never prints, throws or aborts.
+ *   - A plan is not thread-safe: use one plan per host thread / stream.
+ *   - Supported sizes: W even, and both H and W/2 in the table of compiled
+ *     transform lengths (ils_length_supported); every such length is
+ *     2/3/5-smooth.  Other sizes return ILS_ERR_UNSUPPORTED_SIZE.
+ */
+#ifndef ILS_H_
+#define ILS_H_
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define ILS_OK 0
+#define ILS_ERR_INVALID_ARG -1      /* null pointer, bad range, NaN parameter   */
+#define ILS_ERR_UNSUPPORTED_SIZE -2 /* H or W/2 not a compiled length, W odd    */
+#define ILS_ERR_WORKSPACE -3        /* workspace missing or too small           */
+#define ILS_ERR_HIP -4              /* a HIP call failed (see ils_last_error)    */
+#define ILS_ERR_NOT_CALIBRATED -5   /* surrogate gate used without a threshold  */
+
+typedef struct ils_plan ils_plan;
+
+/* One frame of a batched call.  f / out: device pointers, C x H x W float32.
+ * u0: device pointer of the first iterate, or NULL for u^0 = f (Alg. 1). */
+typedef struct ils_frame {
+  const float* f;
+  float* out;
+  int H, W, C;
+  float lambda, p, eps;
+  int N;
+  const float* u0;
+} ils_frame;
+
+/* Human-readable name of a status code (static string). */
+const char* ils_status_string(int status);
+
+/* 1 if L is a compiled transform length (usable as H or as W/2), else 0. */
+int ils_length_supported(int L);
+
+/* 1 if an H x W image is supported (W even, H and W/2 compiled), else 0. */
+int ils_size_supported(int H, int W);
+
+/* Validation of ils_smooth's size and parameter arguments without a plan
+ * (no HIP call): ILS_OK, ILS_ERR_INVALID_ARG or ILS_ERR_UNSUPPORTED_SIZE. */
+int ils_check_args(int H, int W, int C, float lambda, float p, float eps, int N);
+
+/* Bytes of device workspace a plan needs to smooth frames up to
+ * max_H x max_W x max_C, max_frames of them resident at once (single-frame
+ * calls use one slot).  Two half spectra (C x H x (W/2+1) complex64) per
+ * frame plus alignment.  Returns 0 for invalid arguments. */
+size_t ils_workspace_bytes(int max_H, int max_W, int max_C, int max_frames);
+
+/* Exact workspace bytes ils_smooth_batch needs for this list of frames. */
+size_t ils_batch_workspace_bytes(const ils_frame* frames, int n);
+
+/* Create a plan.
+ *   workspace / ws_bytes : caller-owned device memory (e.g. a torch uint8
+ *                          tensor), at least ils_workspace_bytes(...) bytes,
+ *                          256-byte aligned; it must outlive the plan.
+ *   hip_stream           : hipStream_t to enqueue on (NULL = default stream).
+ *   flags                : 0 (reserved).
+ * The plan allocates only its own small device tables (FP64-computed
+ * twiddles and Laplacian eigenvalues) and frees them in ils_plan_destroy.
+ * Returns ILS_OK and sets *plan, or an error with *plan = NULL. */
+int ils_plan_create(ils_plan** plan, int max_H, int max_W, int max_C, int max_frames,
+                    void* workspace, size_t ws_bytes, void* hip_stream, unsigned flags);
+
+/* Change the stream later work is enqueued on. */
+int ils_plan_set_stream(ils_plan* plan, void* hip_stream);
+
+/* Smooth one C x H x W frame: out = u^N of Algorithm 1 with u^0 = f.
+ *   lambda >= 0 finite, 0 < p <= 2, eps > 0 finite, N >= 0.
+ *   N == 0 or lambda == 0 copies f to out (u = f exactly).
+ *   out == f (in place) is allowed; partial overlap is undefined.
+ *   NaN/Inf in f propagate; the output is not clipped. */
+int ils_smooth(ils_plan* plan, const float* f, int H, int W, int C, float lambda, float p,
+               float eps, int N, float* out);
+
+/* As ils_smooth but starting from u^0 = u0 while the data term stays f
+ * (N iterations of Eq. (7)-(9)).  With N = 1 this is the one-iteration map
+ * T(u0) used to judge a candidate output by its fixed-point residual.
+ * u0 may equal f; out must not overlap f or u0 unless out == f == u0. */
+int ils_iterate_from(ils_plan* plan, const float* f, const float* u0, int H, int W, int C,
+                     float lambda, float p, float eps, int N, float* out);
+
+/* Smooth n frames of possibly different sizes and parameters in one
+ * enqueue (one launch per pass over all frames).  frames is a host array,
+ * read during the call.  Each frame obeys the rules of ils_smooth.  The
+ * workspace must hold ils_batch_workspace_bytes(frames, n). */
+int ils_smooth_batch(ils_plan* plan, const ils_frame* frames, int n);
+
+/* Per-frame root-mean-square difference: rms[i] = sqrt(mean((a_i - b_i)^2))
+ * over the count[i] floats of frame i.  a, b, count: host arrays of n device
+ * pointers / counts; rms: device float[n].  Used for the fixed-point
+ * residual of a candidate output. */
+int ils_rms_diff(ils_plan* plan, const float* const* a, const float* const* b,
+                 const long long* count, int n, float* rms);
+
+/* Pass timing.  Between ils_profile_begin and ils_profile_end every pass
+ * launch the plan enqueues is bracketed by two HIP events on the plan's
+ * stream.  ils_profile_end synchronises on the last event and writes, per
+ * pass kind k (0 = first row pass, 1 = middle row pass, 2 = final row pass,
+ * 3 = column pass), the summed duration total_ms[k] and the launch count
+ * count[k] (host arrays of 4).  Timing adds two event records per launch. */
+int ils_profile_begin(ils_plan* plan);
+int ils_profile_end(ils_plan* plan, double* total_ms, int* count);
+
+/* Last asynchronous HIP error seen by the plan (ILS_OK if none); clears it. */
+int ils_last_error(ils_plan* plan);
+
+/* Destroy a plan (NULL is accepted).  Does not free the workspace. */
+int ils_plan_destroy(ils_plan* plan);
+
+/* ---- single-pass entry points (stage checks; same validation rules) ----
+ * spec: device complex64 array C x H x (W/2+1), interleaved (re, im).
+ * ils_debug_rhs_spectrum : spec = 2 * rfft along rows of
+ *     r = f + (lambda c / 2) D^T mu(u0),  mu = mu_paper / c      (Eq. (7), (9))
+ * ils_debug_column_solve : spec_out = column FFT, divide by
+ *     2 H W (1 + (lambda c / 2)(4 sin^2(pi kx/W) + 4 sin^2(pi ky/H))), column
+ *     inverse FFT (unnormalised), applied to spec_in
+ * ils_debug_row_inverse  : out = unnormalised inverse real FFT along rows of
+ *     spec (imaginary parts of the DC and Nyquist bins ignored). */
+int ils_debug_rhs_spectrum(ils_plan* plan, const float* f, const float* u0, int H, int W, int C,
+                           float lambda, float p, float eps, float* spec);
+int ils_debug_column_solve(ils_plan* plan, const float* spec_in, int H, int W, int C,
+                           float lambda, float p, float eps, float* spec_out);
+int ils_debug_row_inverse(ils_plan* plan, const float* spec, int H, int W, int C, float* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ILS_H_ */

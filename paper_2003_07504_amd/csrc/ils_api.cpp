@@ -1,0 +1,655 @@
+// C ABI of the ILS library (declared in include/ils.h): argument validation,
+// plan tables, workspace carve-up and the 2N+1 pass launch sequence of
+// Algorithm 1 (first row pass, then N column passes interleaved with N-1
+// middle row passes, then the final row pass).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <new>
+#include <vector>
+
+#include "../../include/ils.h"
+#include "ils_launch.hpp"
+
+using ilsk::BatchList;
+using ilsk::cf;
+using ilsk::FrameDesc;
+using ilsk::LenOps;
+
+// ---------------------------------------------------------------- registry
+#define ILS_LEN(L, P, Q) const LenOps* ilsk_ops_##L();
+#include "lengths.def"
+#undef ILS_LEN
+
+namespace {
+
+typedef const LenOps* (*OpsFn)();
+const OpsFn kOps[] = {
+#define ILS_LEN(L, P, Q) &ilsk_ops_##L,
+#include "lengths.def"
+#undef ILS_LEN
+};
+const int kLens[] = {
+#define ILS_LEN(L, P, Q) L,
+#include "lengths.def"
+#undef ILS_LEN
+};
+constexpr int kNumLens = sizeof(kLens) / sizeof(kLens[0]);
+
+const LenOps* find_ops(int L) {
+  for (int i = 0; i < kNumLens; ++i)
+    if (kLens[i] == L) return kOps[i]();
+  return nullptr;
+}
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Padded spectrum row length (complex elements): W/2+1 rounded up to 16
+// (128-byte rows).
+inline int spec_ld(int W) { return (int)align_up((size_t)(W / 2 + 1), 16); }
+
+inline size_t frame_ws_bytes(int H, int W, int C) {
+  return align_up(2ull * (size_t)C * (size_t)H * (size_t)spec_ld(W) * sizeof(cf), 256);
+}
+
+// Device-resident header of the batch work lists (descriptors + starts).
+constexpr size_t kBatchHeaderBytes = 1 << 20;
+constexpr int kMaxBatchFrames = 4096;
+
+}  // namespace
+
+// Per-length device tables (offsets into the plan's table buffer).
+struct LenTables {
+  size_t tw, tw2, sx, sy;  // byte offsets
+};
+
+// Pinned host staging for the small host-to-device uploads (batch work
+// lists, reduction jobs).  A slot is reused only after the copy that read it
+// has completed (its event has fired).
+constexpr int kStageSlots = 8;
+constexpr size_t kStageBytes = kBatchHeaderBytes;
+
+struct ils_plan {
+  int max_H, max_W, max_C, max_frames;
+  char* ws;
+  size_t ws_bytes;
+  hipStream_t stream;
+  unsigned flags;
+  int device;
+  int last_error;
+  char* tables;
+  std::map<int, LenTables> tab;
+  char* stage[kStageSlots];
+  hipEvent_t stage_ev[kStageSlots];
+  bool stage_used[kStageSlots];
+  int stage_next;
+  // pass timing
+  bool prof_on;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used;
+  std::vector<int> prof_kind;  // kind of launch i; events 2i, 2i+1
+};
+
+// ----------------------------------------------------------------- helpers
+static int record(ils_plan* plan, hipError_t e) {
+  if (e == hipSuccess) return ILS_OK;
+  if (plan && plan->last_error == ILS_OK) plan->last_error = (int)e;
+  return ILS_ERR_HIP;
+}
+
+// Copy `bytes` of host data to device memory `dst` on the plan's stream via
+// a pinned staging slot.
+static hipError_t stage_upload(ils_plan* plan, void* dst, const void* src, size_t bytes) {
+  if (bytes > kStageBytes) return hipErrorInvalidValue;
+  const int s = plan->stage_next;
+  plan->stage_next = (s + 1) % kStageSlots;
+  if (plan->stage_used[s]) {
+    hipError_t e = hipEventSynchronize(plan->stage_ev[s]);
+    if (e != hipSuccess) return e;
+  }
+  std::memcpy(plan->stage[s], src, bytes);
+  hipError_t e = hipMemcpyAsync(dst, plan->stage[s], bytes, hipMemcpyHostToDevice, plan->stream);
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(plan->stage_ev[s], plan->stream);
+  plan->stage_used[s] = (e == hipSuccess);
+  return e;
+}
+
+// Launch wrapper: brackets the launch with timing events when profiling.
+// kind: 0 first row, 1 middle row, 2 final row, 3 column.
+template <class F>
+static hipError_t timed(ils_plan* plan, int kind, F&& launch) {
+  if (!plan->prof_on) return launch();
+  while (plan->ev_pool.size() < plan->ev_used + 2) {
+    hipEvent_t ev;
+    hipError_t e = hipEventCreate(&ev);
+    if (e != hipSuccess) return e;
+    plan->ev_pool.push_back(ev);
+  }
+  hipEvent_t a = plan->ev_pool[plan->ev_used], b = plan->ev_pool[plan->ev_used + 1];
+  hipError_t e = hipEventRecord(a, plan->stream);
+  if (e != hipSuccess) return e;
+  e = launch();
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(b, plan->stream);
+  if (e != hipSuccess) return e;
+  plan->ev_used += 2;
+  plan->prof_kind.push_back(kind);
+  return hipSuccess;
+}
+
+static void free_plan(ils_plan* plan) {
+  for (hipEvent_t ev : plan->ev_pool) (void)hipEventDestroy(ev);
+  for (int i = 0; i < kStageSlots; ++i) {
+    if (plan->stage_used[i]) (void)hipEventSynchronize(plan->stage_ev[i]);
+    if (plan->stage_ev[i]) (void)hipEventDestroy(plan->stage_ev[i]);
+    if (plan->stage[i]) (void)hipHostFree(plan->stage[i]);
+  }
+  if (plan->tables) (void)hipFree(plan->tables);
+  delete plan;
+}
+
+static bool finite_f(float v) { return std::isfinite(v); }
+
+static int check_params(float lambda, float p, float eps, int N) {
+  if (!finite_f(lambda) || lambda < 0.0f) return ILS_ERR_INVALID_ARG;
+  if (!finite_f(p) || !(p > 0.0f) || p > 2.0f) return ILS_ERR_INVALID_ARG;
+  if (!finite_f(eps) || !(eps > 0.0f)) return ILS_ERR_INVALID_ARG;
+  if (N < 0) return ILS_ERR_INVALID_ARG;
+  return ILS_OK;
+}
+
+static int check_size(const ils_plan* plan, int H, int W, int C) {
+  if (H < 2 || W < 2 || C < 1) return ILS_ERR_INVALID_ARG;
+  if (plan && (H > plan->max_H || W > plan->max_W || C > plan->max_C)) return ILS_ERR_INVALID_ARG;
+  if (!ils_size_supported(H, W)) return ILS_ERR_UNSUPPORTED_SIZE;
+  return ILS_OK;
+}
+
+// Fill a descriptor for one frame; the caller sets f/u0/out and the
+// spectrum pointers.
+static void fill_desc(const ils_plan* plan, FrameDesc& d, int H, int W, int C, float lambda,
+                      float p, float eps) {
+  const double c0 = (double)p * std::pow((double)eps, (double)p / 2.0 - 1.0);  // Eq. (11)
+  const int M = W / 2;
+  const LenTables& tr = plan->tab.at(M);
+  const LenTables& tc = plan->tab.at(H);
+  d.tw_row = reinterpret_cast<const cf*>(plan->tables + tr.tw);
+  d.tw2_row = reinterpret_cast<const cf*>(plan->tables + tr.tw2);
+  d.sx = reinterpret_cast<const float*>(plan->tables + tr.sx);
+  d.tw_col = reinterpret_cast<const cf*>(plan->tables + tc.tw);
+  d.sy = reinterpret_cast<const float*>(plan->tables + tc.sy);
+  d.H = H;
+  d.W = W;
+  d.C = C;
+  d.ldS = spec_ld(W);
+  d.kappa = (float)((double)lambda * c0 / 2.0);
+  d.a_exp = (float)((double)p / 2.0 - 1.0);
+  d.inv_eps = (float)(1.0 / (double)eps);
+  d.col_scale = (float)(1.0 / (2.0 * (double)H * (double)W));
+}
+
+// Enqueue Algorithm 1 for one frame (N >= 1, lambda > 0).
+static int run_frame(ils_plan* plan, const FrameDesc& d, int N) {
+  const LenOps* orow = find_ops(d.W / 2);
+  const LenOps* ocol = find_ops(d.H);
+  hipStream_t st = plan->stream;
+  hipError_t e = timed(plan, 0, [&] { return orow->row(ilsk::ROW_FIRST, d, st); });
+  for (int n = 0; n < N && e == hipSuccess; ++n) {
+    e = timed(plan, 3, [&] { return ocol->col(d, st); });
+    if (e != hipSuccess) break;
+    const int mode = n + 1 < N ? ilsk::ROW_MID : ilsk::ROW_FINAL;
+    e = timed(plan, mode, [&] { return orow->row(mode, d, st); });
+  }
+  return record(plan, e);
+}
+
+// --------------------------------------------------------------- C ABI
+extern "C" {
+
+const char* ils_status_string(int status) {
+  switch (status) {
+    case ILS_OK: return "ok";
+    case ILS_ERR_INVALID_ARG: return "invalid argument";
+    case ILS_ERR_UNSUPPORTED_SIZE: return "unsupported image size";
+    case ILS_ERR_WORKSPACE: return "workspace missing or too small";
+    case ILS_ERR_HIP: return "HIP runtime error";
+    case ILS_ERR_NOT_CALIBRATED: return "surrogate gate not calibrated";
+    default: return "unknown status";
+  }
+}
+
+int ils_length_supported(int L) { return find_ops(L) != nullptr ? 1 : 0; }
+
+int ils_size_supported(int H, int W) {
+  if (H < 2 || W < 2 || (W & 1)) return 0;
+  return ils_length_supported(H) && ils_length_supported(W / 2);
+}
+
+int ils_check_args(int H, int W, int C, float lambda, float p, float eps, int N) {
+  int rc = check_params(lambda, p, eps, N);
+  if (rc != ILS_OK) return rc;
+  return check_size(nullptr, H, W, C);
+}
+
+size_t ils_workspace_bytes(int max_H, int max_W, int max_C, int max_frames) {
+  if (max_H < 2 || max_W < 2 || max_C < 1 || max_frames < 1) return 0;
+  return kBatchHeaderBytes + (size_t)max_frames * frame_ws_bytes(max_H, max_W, max_C);
+}
+
+size_t ils_batch_workspace_bytes(const ils_frame* frames, int n) {
+  if (!frames || n < 1) return 0;
+  size_t s = kBatchHeaderBytes;
+  for (int i = 0; i < n; ++i) {
+    if (frames[i].H < 2 || frames[i].W < 2 || frames[i].C < 1) return 0;
+    s += frame_ws_bytes(frames[i].H, frames[i].W, frames[i].C);
+  }
+  return s;
+}
+
+int ils_plan_create(ils_plan** plan_out, int max_H, int max_W, int max_C, int max_frames,
+                    void* workspace, size_t ws_bytes, void* hip_stream, unsigned flags) {
+  if (!plan_out) return ILS_ERR_INVALID_ARG;
+  *plan_out = nullptr;
+  if (max_H < 2 || max_W < 2 || max_C < 1 || max_frames < 1) return ILS_ERR_INVALID_ARG;
+  if (flags != 0) return ILS_ERR_INVALID_ARG;
+  if (!workspace || ((uintptr_t)workspace & 255)) return ILS_ERR_WORKSPACE;
+  if (ws_bytes < ils_workspace_bytes(max_H, max_W, max_C, max_frames)) return ILS_ERR_WORKSPACE;
+
+  ils_plan* plan = new (std::nothrow) ils_plan();
+  if (!plan) return ILS_ERR_HIP;
+  plan->max_H = max_H;
+  plan->max_W = max_W;
+  plan->max_C = max_C;
+  plan->max_frames = max_frames;
+  plan->ws = static_cast<char*>(workspace);
+  plan->ws_bytes = ws_bytes;
+  plan->stream = static_cast<hipStream_t>(hip_stream);
+  plan->flags = flags;
+  plan->last_error = ILS_OK;
+  plan->tables = nullptr;
+  plan->stage_next = 0;
+  plan->prof_on = false;
+  plan->ev_used = 0;
+  for (int i = 0; i < kStageSlots; ++i) {
+    plan->stage[i] = nullptr;
+    plan->stage_ev[i] = nullptr;
+    plan->stage_used[i] = false;
+  }
+  if (hipGetDevice(&plan->device) != hipSuccess) {
+    delete plan;
+    return ILS_ERR_HIP;
+  }
+  for (int i = 0; i < kStageSlots; ++i) {
+    if (hipHostMalloc((void**)&plan->stage[i], kStageBytes, hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&plan->stage_ev[i], hipEventDisableTiming) != hipSuccess) {
+      free_plan(plan);
+      return ILS_ERR_HIP;
+    }
+  }
+
+  // Tables for every compiled length, computed in double and rounded once.
+  std::vector<char> host;
+  auto put = [&](size_t bytes) {
+    size_t off = align_up(host.size(), 256);
+    host.resize(off + bytes);
+    return off;
+  };
+  for (int i = 0; i < kNumLens; ++i) {
+    const int L = kLens[i];
+    LenTables t;
+    t.tw = put(sizeof(cf) * L);
+    t.tw2 = put(sizeof(cf) * (L + 1));
+    t.sx = put(sizeof(float) * (L + 1));
+    t.sy = put(sizeof(float) * L);
+    cf* tw = reinterpret_cast<cf*>(host.data() + t.tw);
+    for (int j = 0; j < L; ++j) {
+      double a = -2.0 * M_PI * (double)j / (double)L;
+      tw[j] = cf{(float)std::cos(a), (float)std::sin(a)};
+    }
+    cf* tw2 = reinterpret_cast<cf*>(host.data() + t.tw2);
+    for (int k = 0; k <= L; ++k) {
+      double a = -M_PI * (double)k / (double)L;
+      tw2[k] = cf{(float)std::cos(a), (float)std::sin(a)};
+    }
+    // |F(nabla)|^2 for the periodic [1,-1] kernel: 4 sin^2(pi k / n)
+    float* sx = reinterpret_cast<float*>(host.data() + t.sx);
+    for (int k = 0; k <= L; ++k) {
+      double s = std::sin(M_PI * (double)k / (2.0 * L));
+      sx[k] = (float)(4.0 * s * s);
+    }
+    float* sy = reinterpret_cast<float*>(host.data() + t.sy);
+    for (int l = 0; l < L; ++l) {
+      double s = std::sin(M_PI * (double)l / (double)L);
+      sy[l] = (float)(4.0 * s * s);
+    }
+    plan->tab[L] = t;
+  }
+  hipError_t e = hipMalloc(&plan->tables, host.size());
+  if (e == hipSuccess) e = hipMemcpy(plan->tables, host.data(), host.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    free_plan(plan);
+    return ILS_ERR_HIP;
+  }
+  *plan_out = plan;
+  return ILS_OK;
+}
+
+int ils_plan_set_stream(ils_plan* plan, void* hip_stream) {
+  if (!plan) return ILS_ERR_INVALID_ARG;
+  plan->stream = static_cast<hipStream_t>(hip_stream);
+  return ILS_OK;
+}
+
+int ils_plan_destroy(ils_plan* plan) {
+  if (!plan) return ILS_OK;
+  free_plan(plan);
+  return ILS_OK;
+}
+
+int ils_profile_begin(ils_plan* plan) {
+  if (!plan) return ILS_ERR_INVALID_ARG;
+  plan->prof_on = true;
+  plan->ev_used = 0;
+  plan->prof_kind.clear();
+  return ILS_OK;
+}
+
+int ils_profile_end(ils_plan* plan, double* total_ms, int* count) {
+  if (!plan || !total_ms || !count) return ILS_ERR_INVALID_ARG;
+  plan->prof_on = false;
+  for (int k = 0; k < 4; ++k) {
+    total_ms[k] = 0.0;
+    count[k] = 0;
+  }
+  if (plan->ev_used == 0) return ILS_OK;
+  hipError_t e = hipEventSynchronize(plan->ev_pool[plan->ev_used - 1]);
+  if (e != hipSuccess) return record(plan, e);
+  for (size_t i = 0; i < plan->prof_kind.size(); ++i) {
+    float ms = 0.0f;
+    e = hipEventElapsedTime(&ms, plan->ev_pool[2 * i], plan->ev_pool[2 * i + 1]);
+    if (e != hipSuccess) return record(plan, e);
+    total_ms[plan->prof_kind[i]] += ms;
+    count[plan->prof_kind[i]] += 1;
+  }
+  plan->ev_used = 0;
+  plan->prof_kind.clear();
+  return ILS_OK;
+}
+
+int ils_last_error(ils_plan* plan) {
+  if (!plan) return ILS_ERR_INVALID_ARG;
+  hipError_t e = hipStreamQuery(plan->stream);
+  if (e != hipSuccess && e != hipErrorNotReady) record(plan, e);
+  int r = plan->last_error;
+  plan->last_error = ILS_OK;
+  return r;
+}
+
+int ils_iterate_from(ils_plan* plan, const float* f, const float* u0, int H, int W, int C,
+                     float lambda, float p, float eps, int N, float* out) {
+  if (!plan || !f || !u0 || !out) return ILS_ERR_INVALID_ARG;
+  int rc = check_params(lambda, p, eps, N);
+  if (rc != ILS_OK) return rc;
+  rc = check_size(plan, H, W, C);
+  if (rc != ILS_OK) return rc;
+  const size_t need = frame_ws_bytes(H, W, C);
+  if (plan->ws_bytes < kBatchHeaderBytes + need) return ILS_ERR_WORKSPACE;
+  const size_t img = (size_t)C * H * W * sizeof(float);
+  if (N == 0 || lambda == 0.0f) {
+    // u^N = u0 for N = 0; for lambda = 0 the LS problem gives u = f.
+    const float* src = (N == 0) ? u0 : f;
+    if (src == out) return ILS_OK;
+    return record(plan, hipMemcpyAsync(out, src, img, hipMemcpyDeviceToDevice, plan->stream));
+  }
+  FrameDesc d;
+  fill_desc(plan, d, H, W, C, lambda, p, eps);
+  d.f = f;
+  d.u0 = u0;
+  d.out = out;
+  char* base = plan->ws + kBatchHeaderBytes;
+  const size_t half = (size_t)C * H * d.ldS * sizeof(cf);
+  d.specA = reinterpret_cast<cf*>(base);
+  d.specB = reinterpret_cast<cf*>(base + half);
+  return run_frame(plan, d, N);
+}
+
+int ils_smooth(ils_plan* plan, const float* f, int H, int W, int C, float lambda, float p,
+               float eps, int N, float* out) {
+  return ils_iterate_from(plan, f, f, H, W, C, lambda, p, eps, N, out);
+}
+
+int ils_smooth_batch(ils_plan* plan, const ils_frame* frames, int n) {
+  if (!plan || !frames || n < 1) return ILS_ERR_INVALID_ARG;
+  if (n > plan->max_frames || n > kMaxBatchFrames) return ILS_ERR_INVALID_ARG;
+  for (int i = 0; i < n; ++i) {
+    const ils_frame& fr = frames[i];
+    if (!fr.f || !fr.out) return ILS_ERR_INVALID_ARG;
+    int rc = check_params(fr.lambda, fr.p, fr.eps, fr.N);
+    if (rc != ILS_OK) return rc;
+    rc = check_size(plan, fr.H, fr.W, fr.C);
+    if (rc != ILS_OK) return rc;
+  }
+  const size_t need = ils_batch_workspace_bytes(frames, n);
+  if (need == 0 || plan->ws_bytes < need) return ILS_ERR_WORKSPACE;
+
+  // Descriptors for every frame that needs iterations; trivial frames copy.
+  std::vector<FrameDesc> descs;
+  std::vector<int> iters;
+  char* base = plan->ws + kBatchHeaderBytes;
+  size_t off = 0;
+  for (int i = 0; i < n; ++i) {
+    const ils_frame& fr = frames[i];
+    const float* u0 = fr.u0 ? fr.u0 : fr.f;
+    if (fr.N == 0 || fr.lambda == 0.0f) {
+      const float* src = (fr.N == 0) ? u0 : fr.f;
+      if (src != fr.out) {
+        hipError_t e = hipMemcpyAsync(fr.out, src, (size_t)fr.C * fr.H * fr.W * sizeof(float),
+                                      hipMemcpyDeviceToDevice, plan->stream);
+        if (e != hipSuccess) return record(plan, e);
+      }
+      off += frame_ws_bytes(fr.H, fr.W, fr.C);
+      continue;
+    }
+    FrameDesc d;
+    fill_desc(plan, d, fr.H, fr.W, fr.C, fr.lambda, fr.p, fr.eps);
+    d.f = fr.f;
+    d.u0 = u0;
+    d.out = fr.out;
+    const size_t half = (size_t)fr.C * fr.H * d.ldS * sizeof(cf);
+    d.specA = reinterpret_cast<cf*>(base + off);
+    d.specB = reinterpret_cast<cf*>(base + off + half);
+    off += frame_ws_bytes(fr.H, fr.W, fr.C);
+    descs.push_back(d);
+    iters.push_back(fr.N);
+  }
+  if (descs.empty()) return ILS_OK;
+
+  // Group frames into classes of equal (row length, column length, N):
+  // one launch per pass per class, each a persistent grid over the class's
+  // (frame, channel, band) work list.
+  struct Class {
+    int M, H, N;
+    std::vector<int> idx;
+  };
+  std::vector<Class> classes;
+  for (size_t i = 0; i < descs.size(); ++i) {
+    int M = descs[i].W / 2, H = descs[i].H, N = iters[i];
+    size_t c = 0;
+    for (; c < classes.size(); ++c)
+      if (classes[c].M == M && classes[c].H == H && classes[c].N == N) break;
+    if (c == classes.size()) classes.push_back(Class{M, H, N, {}});
+    classes[c].idx.push_back((int)i);
+  }
+
+  // Host image of the batch header: per class, descriptors then three start
+  // arrays (row FIRST/MID, row FINAL, column).
+  std::vector<char> hdr;
+  auto put = [&](const void* src, size_t bytes) {
+    size_t o = align_up(hdr.size(), 64);
+    hdr.resize(o + bytes);
+    std::memcpy(hdr.data() + o, src, bytes);
+    return o;
+  };
+  struct Launch {
+    const LenOps* orow;
+    const LenOps* ocol;
+    int N;
+    BatchList row, fin, col;
+  };
+  std::vector<Launch> launches;
+  std::vector<size_t> offs;  // (desc, row starts, fin starts, col starts) per class
+  for (const Class& cl : classes) {
+    Launch L;
+    L.orow = find_ops(cl.M);
+    L.ocol = find_ops(cl.H);
+    L.N = cl.N;
+    std::vector<FrameDesc> cd;
+    std::vector<int> srow(1, 0), sfin(1, 0), scol(1, 0);
+    for (int i : cl.idx) {
+      const FrameDesc& d = descs[i];
+      cd.push_back(d);
+      const int gr = L.orow->row_rows[ilsk::ROW_MID], gf = L.orow->row_rows[ilsk::ROW_FINAL];
+      const int sc = L.ocol->col_cols;
+      srow.push_back(srow.back() + d.C * ((d.H + gr - 1) / gr));
+      sfin.push_back(sfin.back() + d.C * ((d.H + gf - 1) / gf));
+      scol.push_back(scol.back() + d.C * ((d.W / 2 + 1 + sc - 1) / sc));
+    }
+    offs.push_back(put(cd.data(), cd.size() * sizeof(FrameDesc)));
+    offs.push_back(put(srow.data(), srow.size() * sizeof(int)));
+    offs.push_back(put(sfin.data(), sfin.size() * sizeof(int)));
+    offs.push_back(put(scol.data(), scol.size() * sizeof(int)));
+    const int nf = (int)cl.idx.size();
+    L.row = BatchList{nullptr, nullptr, nf, srow.back()};
+    L.fin = BatchList{nullptr, nullptr, nf, sfin.back()};
+    L.col = BatchList{nullptr, nullptr, nf, scol.back()};
+    launches.push_back(L);
+  }
+  if (hdr.size() > kBatchHeaderBytes) return ILS_ERR_WORKSPACE;
+  for (size_t c = 0; c < launches.size(); ++c) {
+    const FrameDesc* dd = reinterpret_cast<const FrameDesc*>(plan->ws + offs[4 * c]);
+    launches[c].row.descs = dd;
+    launches[c].fin.descs = dd;
+    launches[c].col.descs = dd;
+    launches[c].row.starts = reinterpret_cast<const int*>(plan->ws + offs[4 * c + 1]);
+    launches[c].fin.starts = reinterpret_cast<const int*>(plan->ws + offs[4 * c + 2]);
+    launches[c].col.starts = reinterpret_cast<const int*>(plan->ws + offs[4 * c + 3]);
+  }
+  hipError_t e = stage_upload(plan, plan->ws, hdr.data(), hdr.size());
+  if (e != hipSuccess) return record(plan, e);
+
+  // Persistent grid: enough blocks to fill every CU a few times over.
+  int cus = 256;
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, plan->device);
+  auto grid_for = [&](int total) { return total < 8 * cus ? total : 8 * cus; };
+  int maxN = 0;
+  for (const Launch& L : launches) maxN = L.N > maxN ? L.N : maxN;
+  // Pass-major order: every class's pass k is enqueued before any pass k+1.
+  hipStream_t st = plan->stream;
+  for (const Launch& L : launches) {
+    e = timed(plan, 0, [&] { return L.orow->row_batch(ilsk::ROW_FIRST, L.row, grid_for(L.row.total), st); });
+    if (e != hipSuccess) return record(plan, e);
+  }
+  for (int n = 0; n < maxN; ++n) {
+    for (const Launch& L : launches) {
+      if (n >= L.N) continue;
+      e = timed(plan, 3, [&] { return L.ocol->col_batch(L.col, grid_for(L.col.total), st); });
+      if (e != hipSuccess) return record(plan, e);
+    }
+    for (const Launch& L : launches) {
+      if (n >= L.N) continue;
+      if (n + 1 < L.N)
+        e = timed(plan, 1, [&] { return L.orow->row_batch(ilsk::ROW_MID, L.row, grid_for(L.row.total), st); });
+      else
+        e = timed(plan, 2, [&] { return L.orow->row_batch(ilsk::ROW_FINAL, L.fin, grid_for(L.fin.total), st); });
+      if (e != hipSuccess) return record(plan, e);
+    }
+  }
+  return ILS_OK;
+}
+
+// ------------------------------------------------------------ debug passes
+int ils_debug_rhs_spectrum(ils_plan* plan, const float* f, const float* u0, int H, int W, int C,
+                           float lambda, float p, float eps, float* spec) {
+  if (!plan || !f || !u0 || !spec) return ILS_ERR_INVALID_ARG;
+  int rc = check_params(lambda, p, eps, 1);
+  if (rc == ILS_OK) rc = check_size(plan, H, W, C);
+  if (rc != ILS_OK) return rc;
+  if (plan->ws_bytes < kBatchHeaderBytes + frame_ws_bytes(H, W, C)) return ILS_ERR_WORKSPACE;
+  FrameDesc d;
+  fill_desc(plan, d, H, W, C, lambda, p, eps);
+  d.f = f;
+  d.u0 = u0;
+  d.out = nullptr;
+  char* base = plan->ws + kBatchHeaderBytes;
+  d.specA = reinterpret_cast<cf*>(base);
+  d.specB = reinterpret_cast<cf*>(base + (size_t)C * H * d.ldS * sizeof(cf));
+  hipError_t e = find_ops(W / 2)->row(ilsk::ROW_FIRST, d, plan->stream);
+  if (e == hipSuccess)
+    e = hipMemcpy2DAsync(spec, (size_t)(W / 2 + 1) * sizeof(cf), d.specA, (size_t)d.ldS * sizeof(cf),
+                         (size_t)(W / 2 + 1) * sizeof(cf), (size_t)C * H, hipMemcpyDeviceToDevice,
+                         plan->stream);
+  return record(plan, e);
+}
+
+int ils_debug_column_solve(ils_plan* plan, const float* spec_in, int H, int W, int C, float lambda,
+                           float p, float eps, float* spec_out) {
+  if (!plan || !spec_in || !spec_out) return ILS_ERR_INVALID_ARG;
+  int rc = check_params(lambda, p, eps, 1);
+  if (rc == ILS_OK) rc = check_size(plan, H, W, C);
+  if (rc != ILS_OK) return rc;
+  if (plan->ws_bytes < kBatchHeaderBytes + frame_ws_bytes(H, W, C)) return ILS_ERR_WORKSPACE;
+  FrameDesc d;
+  fill_desc(plan, d, H, W, C, lambda, p, eps);
+  d.f = d.u0 = nullptr;
+  d.out = nullptr;
+  char* base = plan->ws + kBatchHeaderBytes;
+  d.specA = reinterpret_cast<cf*>(base);
+  d.specB = reinterpret_cast<cf*>(base + (size_t)C * H * d.ldS * sizeof(cf));
+  const size_t rowb = (size_t)(W / 2 + 1) * sizeof(cf);
+  hipError_t e = hipMemcpy2DAsync(d.specA, (size_t)d.ldS * sizeof(cf), spec_in, rowb, rowb,
+                                  (size_t)C * H, hipMemcpyDeviceToDevice, plan->stream);
+  if (e == hipSuccess) e = find_ops(H)->col(d, plan->stream);
+  if (e == hipSuccess)
+    e = hipMemcpy2DAsync(spec_out, rowb, d.specB, (size_t)d.ldS * sizeof(cf), rowb, (size_t)C * H,
+                         hipMemcpyDeviceToDevice, plan->stream);
+  return record(plan, e);
+}
+
+int ils_debug_row_inverse(ils_plan* plan, const float* spec, int H, int W, int C, float* out) {
+  if (!plan || !spec || !out) return ILS_ERR_INVALID_ARG;
+  int rc = check_size(plan, H, W, C);
+  if (rc != ILS_OK) return rc;
+  if (plan->ws_bytes < kBatchHeaderBytes + frame_ws_bytes(H, W, C)) return ILS_ERR_WORKSPACE;
+  FrameDesc d;
+  fill_desc(plan, d, H, W, C, 1.0f, 1.0f, 1e-4f);
+  d.f = d.u0 = nullptr;
+  d.out = out;
+  char* base = plan->ws + kBatchHeaderBytes;
+  d.specA = reinterpret_cast<cf*>(base + (size_t)C * H * d.ldS * sizeof(cf));
+  d.specB = reinterpret_cast<cf*>(base);
+  const size_t rowb = (size_t)(W / 2 + 1) * sizeof(cf);
+  hipError_t e = hipMemcpy2DAsync(d.specB, (size_t)d.ldS * sizeof(cf), spec, rowb, rowb, (size_t)C * H,
+                                  hipMemcpyDeviceToDevice, plan->stream);
+  if (e == hipSuccess) e = find_ops(W / 2)->row(ilsk::ROW_FINAL, d, plan->stream);
+  return record(plan, e);
+}
+
+}  // extern "C"
+
+// Scratch area for small auxiliary kernels (the batch header region of the
+// workspace; stream order separates its users).
+int ilsk_plan_scratch(ils_plan* plan, void** scratch, size_t* bytes, void** stream) {
+  if (!plan) return ILS_ERR_INVALID_ARG;
+  *scratch = plan->ws;
+  *bytes = kBatchHeaderBytes;
+  *stream = plan->stream;
+  return ILS_OK;
+}
+
+int ilsk_plan_upload(ils_plan* plan, void* dst, const void* src, size_t bytes) {
+  return record(plan, stage_upload(plan, dst, src, bytes));
+}

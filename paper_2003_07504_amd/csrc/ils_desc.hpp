@@ -1,0 +1,37 @@
+// Per-frame descriptor shared by the host planner and the kernels.
+#pragma once
+
+#include <cstdint>
+
+namespace ilsk {
+
+struct cf;
+
+// One frame (all of its channels) of one ILS call.  Layouts:
+//   f, u0, out : C x H x W float32, row-major, channel stride H*W
+//   specA/specB: C x H x ldS complex64 (half spectrum, W/2+1 used columns
+//                per row, ldS >= W/2+1), channel stride H*ldS
+// The row passes read specB and write specA; the column pass reads specA
+// and writes specB.
+struct FrameDesc {
+  const float* f;    // data term of the LS problem
+  const float* u0;   // first iterate (normally == f)
+  float* out;        // result u^N
+  cf* specA;
+  cf* specB;
+  const cf* tw_row;   // exp(-2 pi i j / M), j < M          (M = W/2)
+  const cf* tw2_row;  // exp(-pi i k / M),  k <= M
+  const float* sx;    // 4 sin^2(pi k / W), k <= M
+  const cf* tw_col;   // exp(-2 pi i j / H), j < H
+  const float* sy;    // 4 sin^2(pi l / H), l < H
+  int H, W, C, ldS;
+  float kappa;      // lambda * c / 2, c = p eps^(p/2 - 1)
+  float a_exp;      // p/2 - 1
+  float inv_eps;    // 1 / eps
+  float col_scale;  // 1 / (2 H W): inverse-transform normalisation (and the
+                    // factor 2 the row R2C leaves in its output)
+};
+
+enum RowMode : int { ROW_FIRST = 0, ROW_MID = 1, ROW_FINAL = 2 };
+
+}  // namespace ilsk

@@ -1,0 +1,372 @@
+// The two fused passes of one ILS iteration (Algorithm 1), as device bodies.
+//
+// Row pass (band of G output rows of one channel):
+//   MID   : spectrum rows y0-1 .. y0+G  --C2R-->  u^n rows (LDS)
+//           stencil: forward differences, mu (Eq. (7)), adjoint differences
+//           r = f + kappa * D^T mu                     (Eq. (9) numerator,
+//                                                       one-FFT form, Sec. 3.2)
+//           r rows y0 .. y0+G-1  --R2C-->  spectrum rows
+//   FIRST : as MID with u^0 rows read from memory instead of the C2R
+//   FINAL : spectrum rows --C2R--> u^N rows written to the output
+// Column pass (tile of S spectrum columns of one channel):
+//   forward column DFT, divide by 1 + kappa (Sx + Sy) (Eq. (9) denominator)
+//   and the inverse normalisation, inverse column DFT.
+//
+// A length-M complex DFT is split M = P * Q (four-step): the element index
+// n = Q n1 + t is held by lane t (register n1) in "spatial" layout; stage A
+// is a P-point register DFT per lane, a twiddle exp(-+2 pi i t k1 / M), one
+// LDS exchange, and stage B a Q-point register DFT per lane k1, giving
+// X[k1 + P k2] in register k2.  The inverse runs the same steps backwards,
+// so no digit reversal is ever materialised.
+#pragma once
+
+#include "fft_reg.hpp"
+#include "ils_desc.hpp"
+
+namespace ilsk {
+
+__device__ __forceinline__ int imax(int a, int b) { return a > b ? a : b; }
+__device__ __forceinline__ int imin(int a, int b) { return a < b ? a : b; }
+
+// Normalised half-quadratic variable  mu / c = g (1 - (1 + g^2/eps)^(p/2 - 1))
+// (Eq. (7) divided by c = p eps^(p/2-1)); base-2 log/exp on the hardware
+// transcendental unit.
+__device__ __forceinline__ float mu_ns(float g, float a_exp, float inv_eps) {
+  float t = fmaf(g * g, inv_eps, 1.0f);
+  float pw = __builtin_amdgcn_exp2f(a_exp * __builtin_amdgcn_logf(t));
+  return fmaf(-g, pw, g);
+}
+
+template <int P, int Q>
+struct RowGeom {
+  static constexpr int M = P * Q;
+  static constexpr int T = P > Q ? P : Q;  // lanes per row slot
+  static constexpr int QP = Q | 1;         // padded exchange row (odd => conflict-free)
+  static constexpr int SLOT_F = 2 * P * QP;  // floats of LDS per row slot (>= W)
+};
+
+// Rows per row-pass workgroup: two workgroups per CU when the LDS allows it.
+template <int P, int Q>
+constexpr int row_band() {
+  constexpr int bytes = 4 * RowGeom<P, Q>::SLOT_F;
+  int g = 76000 / bytes - 2;
+  if (g < 4) g = 150000 / bytes - 2;
+  if (g > 14) g = 14;
+  if (g < 1) g = 1;
+  return g;
+}
+
+template <int P, int Q>
+struct ColGeom {
+  static constexpr int H = P * Q;
+  static constexpr int T = P > Q ? P : Q;
+  static constexpr int pick_s() {
+    if (P * Q * 16 * 8 <= 40000) return 16;
+    if (P * (Q * 8 + 8) * 8 <= 80000) return 8;
+    return 4;
+  }
+  static constexpr int S = pick_s();
+  // stride between k1 blocks of the exchange (in complex elements), padded so
+  // that successive k1 groups land on different LDS banks
+  static constexpr int KS = (S >= 16) ? Q * S : Q * S + ((S - (Q * S) % 16) + 16) % 16;
+  static constexpr int LDS_F = 2 * P * KS;
+};
+
+// --------------------------------------------------------------------------
+// Row pass, modes FIRST and MID.  Block = (G + 2) slots x T lanes.
+// Slot s holds row y0 - 1 + s (periodic), s = 0 .. Gv + 1.
+// --------------------------------------------------------------------------
+template <int P, int Q, int G, int MODE>
+__device__ __forceinline__ void row_body(const FrameDesc& d, int band, int ch, float* smem) {
+  using Geo = RowGeom<P, Q>;
+  constexpr int M = Geo::M, T = Geo::T, QP = Geo::QP, SLOT_F = Geo::SLOT_F;
+  const int H = d.H;
+  const int W = 2 * M;
+  const int ldS = d.ldS;
+  const int y0 = band * G;
+  const int Gv = imin(G, H - y0);
+  const int tid = threadIdx.x;
+  const int slot = tid / T;
+  const int lane = tid - slot * T;
+  float* sl = smem + slot * SLOT_F;
+  cf* slc = reinterpret_cast<cf*>(sl);
+  const bool in_slot = slot <= Gv + 1;
+  int yrow = y0 - 1 + slot;
+  yrow = yrow < 0 ? yrow + H : (yrow >= H ? yrow - H : yrow);
+  if (!in_slot) yrow = 0;
+
+  const cf* tw = d.tw_row;
+  const cf* tw2 = d.tw2_row;
+
+  if constexpr (MODE == ROW_FIRST) {
+    const float* u0 = d.u0 + (size_t)ch * H * W;
+    for (int i = tid; i < (Gv + 2) * M; i += blockDim.x) {
+      int s = i / M, j = i - s * M;
+      int yy = y0 - 1 + s;
+      yy = yy < 0 ? yy + H : (yy >= H ? yy - H : yy);
+      float2 v = *reinterpret_cast<const float2*>(u0 + (size_t)yy * W + 2 * j);
+      reinterpret_cast<float2*>(smem + s * SLOT_F)[j] = v;
+    }
+  } else {
+    // ---- C2R of this slot's row: pre-process + stage A' (Q-point inverse)
+    if (in_slot && lane < P) {
+      const int k1 = lane;
+      const cf* X = d.specB + (size_t)ch * H * ldS + (size_t)yrow * ldS;
+      cf v[Q];
+      static_for<Q>([&](auto k2c) {
+        constexpr int k2 = decltype(k2c)::value;
+        const int k = k1 + P * k2;
+        cf a = X[k];
+        cf b = X[M - k];
+        if (k2 == 0 && k1 == 0) {  // DC and Nyquist bins: real parts only
+          a.y = 0.0f;
+          b.y = 0.0f;
+        }
+        cf bc = {b.x, -b.y};
+        cf e = cadd(a, bc);
+        cf o = cmulc(csub(a, bc), tw2[k]);  // (X[k] - conj X[M-k]) exp(+i pi k / M)
+        v[k2] = {e.x - o.y, e.y + o.x};    // e + i o
+      });
+      dft<Q, +1>(v);
+      static_for<Q>([&](auto tc) {
+        constexpr int t = decltype(tc)::value;
+        cf w = (t == 0 || k1 == 0) ? cf{1.0f, 0.0f} : tw[t * k1];
+        slc[k1 * QP + t] = cmulc(v[t], w);
+      });
+    }
+    __syncthreads();
+    cf z[P];
+    if (in_slot && lane < Q) {
+      const int t = lane;
+      static_for<P>([&](auto k1c) {
+        constexpr int k1 = decltype(k1c)::value;
+        z[k1] = slc[k1 * QP + t];
+      });
+      dft<P, +1>(z);
+    }
+    __syncthreads();
+    if (in_slot && lane < Q) {
+      const int t = lane;
+      float2* u2 = reinterpret_cast<float2*>(sl);
+      static_for<P>([&](auto n1c) {
+        constexpr int n1 = decltype(n1c)::value;
+        u2[Q * n1 + t] = make_float2(z[n1].x, z[n1].y);
+      });
+    }
+  }
+  __syncthreads();
+
+  // ---- stencil + stage A (P-point forward) for output slots 1..Gv
+  const bool out_slot = slot >= 1 && slot <= Gv;
+  const int yout = y0 - 1 + slot;
+  cf r[P];
+  if (out_slot && lane < Q) {
+    const int t = lane;
+    const float2* uc = reinterpret_cast<const float2*>(sl);
+    const float2* uu = reinterpret_cast<const float2*>(sl - SLOT_F);
+    const float2* ud = reinterpret_cast<const float2*>(sl + SLOT_F);
+    const float2* frow = reinterpret_cast<const float2*>(d.f + (size_t)ch * H * W + (size_t)yout * W);
+    const float a_exp = d.a_exp, inv_eps = d.inv_eps, kappa = d.kappa;
+    static_for<P>([&](auto n1c) {
+      constexpr int n1 = decltype(n1c)::value;
+      const int j = Q * n1 + t;
+      const int jm = (j == 0) ? M - 1 : j - 1;
+      const int jp = (j == M - 1) ? 0 : j + 1;
+      float2 c = uc[j], l = uc[jm], rr = uc[jp], up = uu[j], dn = ud[j];
+      float mxl = mu_ns(c.x - l.y, a_exp, inv_eps);
+      float mx0 = mu_ns(c.y - c.x, a_exp, inv_eps);
+      float mx1 = mu_ns(rr.x - c.y, a_exp, inv_eps);
+      float myu0 = mu_ns(c.x - up.x, a_exp, inv_eps);
+      float myu1 = mu_ns(c.y - up.y, a_exp, inv_eps);
+      float myd0 = mu_ns(dn.x - c.x, a_exp, inv_eps);
+      float myd1 = mu_ns(dn.y - c.y, a_exp, inv_eps);
+      float d0 = (mxl - mx0) + (myu0 - myd0);
+      float d1 = (mx0 - mx1) + (myu1 - myd1);
+      float2 fv = frow[j];
+      r[n1] = {fmaf(kappa, d0, fv.x), fmaf(kappa, d1, fv.y)};
+    });
+    dft<P, -1>(r);
+    static_for<P>([&](auto k1c) {
+      constexpr int k1 = decltype(k1c)::value;
+      if (k1 != 0 && t != 0) r[k1] = cmul(r[k1], tw[t * k1]);
+    });
+  }
+  __syncthreads();
+  if (out_slot && lane < Q) {
+    const int t = lane;
+    static_for<P>([&](auto k1c) {
+      constexpr int k1 = decltype(k1c)::value;
+      slc[k1 * QP + t] = r[k1];
+    });
+  }
+  __syncthreads();
+  cf zz[Q];
+  if (out_slot && lane < P) {
+    const int k1 = lane;
+    static_for<Q>([&](auto tc) {
+      constexpr int t = decltype(tc)::value;
+      zz[t] = slc[k1 * QP + t];
+    });
+    dft<Q, -1>(zz);
+  }
+  __syncthreads();
+  if (out_slot && lane < P) {
+    const int k1 = lane;
+    static_for<Q>([&](auto k2c) {
+      constexpr int k2 = decltype(k2c)::value;
+      slc[k1 + P * k2] = zz[k2];
+    });
+  }
+  __syncthreads();
+  // ---- R2C post-process: X'[k] = E - i W_2M^k D  (= 2 X[k]),  k = 0..M
+  if (out_slot) {
+    cf* Xo = d.specA + (size_t)ch * H * ldS + (size_t)yout * ldS;
+    for (int k = lane; k <= M; k += T) {
+      cf A = slc[k == M ? 0 : k];
+      cf B = slc[k == 0 ? 0 : M - k];
+      B.y = -B.y;
+      cf E = cadd(A, B), D = csub(A, B);
+      cf wD = cmul(D, tw2[k]);
+      Xo[k] = {E.x + wD.y, E.y - wD.x};  // E - i wD
+    }
+  }
+}
+
+// --------------------------------------------------------------------------
+// Row pass, mode FINAL: C2R of G rows, written to the output image.
+// Block = G slots x T lanes; slot s holds row y0 + s.
+// --------------------------------------------------------------------------
+template <int P, int Q, int G>
+__device__ __forceinline__ void row_final_body(const FrameDesc& d, int band, int ch, float* smem) {
+  using Geo = RowGeom<P, Q>;
+  constexpr int M = Geo::M, T = Geo::T, QP = Geo::QP, SLOT_F = Geo::SLOT_F;
+  const int H = d.H;
+  const int W = 2 * M;
+  const int ldS = d.ldS;
+  const int y0 = band * G;
+  const int Gv = imin(G, H - y0);
+  const int tid = threadIdx.x;
+  const int slot = tid / T;
+  const int lane = tid - slot * T;
+  cf* slc = reinterpret_cast<cf*>(smem + slot * SLOT_F);
+  const bool in_slot = slot < Gv;
+  const int yrow = in_slot ? y0 + slot : 0;
+  const cf* tw = d.tw_row;
+  const cf* tw2 = d.tw2_row;
+
+  if (in_slot && lane < P) {
+    const int k1 = lane;
+    const cf* X = d.specB + (size_t)ch * H * ldS + (size_t)yrow * ldS;
+    cf v[Q];
+    static_for<Q>([&](auto k2c) {
+      constexpr int k2 = decltype(k2c)::value;
+      const int k = k1 + P * k2;
+      cf a = X[k];
+      cf b = X[M - k];
+      if (k2 == 0 && k1 == 0) {
+        a.y = 0.0f;
+        b.y = 0.0f;
+      }
+      cf bc = {b.x, -b.y};
+      cf e = cadd(a, bc);
+      cf o = cmulc(csub(a, bc), tw2[k]);
+      v[k2] = {e.x - o.y, e.y + o.x};
+    });
+    dft<Q, +1>(v);
+    static_for<Q>([&](auto tc) {
+      constexpr int t = decltype(tc)::value;
+      cf w = (t == 0 || k1 == 0) ? cf{1.0f, 0.0f} : tw[t * k1];
+      slc[k1 * QP + t] = cmulc(v[t], w);
+    });
+  }
+  __syncthreads();
+  if (in_slot && lane < Q) {
+    const int t = lane;
+    cf z[P];
+    static_for<P>([&](auto k1c) {
+      constexpr int k1 = decltype(k1c)::value;
+      z[k1] = slc[k1 * QP + t];
+    });
+    dft<P, +1>(z);
+    float2* orow = reinterpret_cast<float2*>(d.out + (size_t)ch * H * W + (size_t)yrow * W);
+    static_for<P>([&](auto n1c) {
+      constexpr int n1 = decltype(n1c)::value;
+      orow[Q * n1 + t] = make_float2(z[n1].x, z[n1].y);
+    });
+  }
+}
+
+// --------------------------------------------------------------------------
+// Column pass.  Block = S columns x T lanes, lane id = s + S * j.
+// --------------------------------------------------------------------------
+template <int P, int Q>
+__device__ __forceinline__ void col_body(const FrameDesc& d, int tile, int ch, float* smem) {
+  using Geo = ColGeom<P, Q>;
+  constexpr int H = Geo::H, S = Geo::S, KS = Geo::KS;
+  const int ldS = d.ldS;
+  const int Wh = d.W / 2 + 1;
+  const int tid = threadIdx.x;
+  const int s = tid % S;
+  const int j = tid / S;
+  const int c = tile * S + s;
+  const bool col_ok = c < Wh;
+  const int cc = col_ok ? c : 0;
+  const cf* in = d.specA + (size_t)ch * H * ldS + cc;
+  cf* out = d.specB + (size_t)ch * H * ldS + cc;
+  cf* ex = reinterpret_cast<cf*>(smem);
+  const cf* tw = d.tw_col;
+
+  if (j < Q) {  // stage A: lane n2 = j, rows Q n1 + n2
+    cf x[P];
+    static_for<P>([&](auto n1c) {
+      constexpr int n1 = decltype(n1c)::value;
+      x[n1] = col_ok ? in[(size_t)(Q * n1 + j) * ldS] : cf{0.0f, 0.0f};
+    });
+    dft<P, -1>(x);
+    static_for<P>([&](auto k1c) {
+      constexpr int k1 = decltype(k1c)::value;
+      cf v = (k1 == 0 || j == 0) ? x[k1] : cmul(x[k1], tw[j * k1]);
+      ex[k1 * KS + j * S + s] = v;
+    });
+  }
+  __syncthreads();
+  if (j < P) {  // stage B: lane k1 = j; forward, divide, inverse
+    cf y[Q];
+    static_for<Q>([&](auto n2c) {
+      constexpr int n2 = decltype(n2c)::value;
+      y[n2] = ex[j * KS + n2 * S + s];
+    });
+    dft<Q, -1>(y);
+    const float sxk = d.sx[cc];
+    const float kappa = d.kappa, scale = d.col_scale;
+    static_for<Q>([&](auto k2c) {
+      constexpr int k2 = decltype(k2c)::value;
+      float den = fmaf(kappa, sxk + d.sy[j + P * k2], 1.0f);
+      float fac = scale * __builtin_amdgcn_rcpf(den);
+      y[k2] = cscale(y[k2], fac);
+    });
+    dft<Q, +1>(y);
+    static_for<Q>([&](auto n2c) {
+      constexpr int n2 = decltype(n2c)::value;
+      cf v = (n2 == 0 || j == 0) ? y[n2] : cmulc(y[n2], tw[n2 * j]);
+      ex[j * KS + n2 * S + s] = v;  // same slots this lane just read
+    });
+  }
+  __syncthreads();
+  if (j < Q) {  // stage B': lane n2 = j, P-point inverse over k1
+    cf x[P];
+    static_for<P>([&](auto k1c) {
+      constexpr int k1 = decltype(k1c)::value;
+      x[k1] = ex[k1 * KS + j * S + s];
+    });
+    dft<P, +1>(x);
+    if (col_ok) {
+      static_for<P>([&](auto n1c) {
+        constexpr int n1 = decltype(n1c)::value;
+        out[(size_t)(Q * n1 + j) * ldS] = x[n1];
+      });
+    }
+  }
+}
+
+}  // namespace ilsk

@@ -1,0 +1,220 @@
+"""Python binding of the ILS library: argument marshalling only.
+
+Every step of the smoothing runs in the HIP kernels of libils.so; PyTorch
+provides device memory (the workspace and the images) and the stream.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Sequence
+
+import torch
+
+from ._lib import IlsFrame, check, load
+
+__all__ = ["Plan", "smooth", "size_supported", "workspace_bytes"]
+
+
+def _as_chw(t: torch.Tensor, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on a GPU device")
+    if t.dtype != torch.float32:
+        raise ValueError(f"{name} must be float32")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.dim() == 2:
+        return t.unsqueeze(0)
+    if t.dim() != 3:
+        raise ValueError(f"{name} must be (H, W) or (C, H, W)")
+    return t
+
+
+def size_supported(H: int, W: int) -> bool:
+    return bool(load().ils_size_supported(int(H), int(W)))
+
+
+def workspace_bytes(max_H: int, max_W: int, max_C: int = 3, max_frames: int = 1) -> int:
+    return int(load().ils_workspace_bytes(max_H, max_W, max_C, max_frames))
+
+
+def _stream_ptr(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+class Plan:
+    """A plan and its workspace for frames up to max_H x max_W x max_C;
+    max_frames frames may be resident in one batched call."""
+
+    def __init__(self, max_H: int, max_W: int, max_C: int = 3, max_frames: int = 1, device=None,
+                 ws_bytes: int | None = None):
+        self._lib = load()
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        need = int(self._lib.ils_workspace_bytes(max_H, max_W, max_C, max_frames))
+        if need == 0:
+            raise ValueError("invalid plan limits")
+        ws_bytes = max(need, int(ws_bytes or 0))
+        self.workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=self.device)
+        self.max_H, self.max_W, self.max_C, self.max_frames = max_H, max_W, max_C, max_frames
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            check(self._lib.ils_plan_create(ctypes.byref(h), max_H, max_W, max_C, max_frames,
+                                            ctypes.c_void_p(self.workspace.data_ptr()), ws_bytes,
+                                            ctypes.c_void_p(_stream_ptr(self.device)), 0),
+                  "ils_plan_create")
+        self._h = h
+
+    # -- lifetime ----------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            torch.cuda.synchronize(self.device)
+            self._lib.ils_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _bind_stream(self):
+        check(self._lib.ils_plan_set_stream(self._h, ctypes.c_void_p(_stream_ptr(self.device))),
+              "ils_plan_set_stream")
+
+    def last_error(self) -> int:
+        return int(self._lib.ils_last_error(self._h))
+
+    PASS_KINDS = ("row_first", "row_mid", "row_final", "column")
+
+    def profile_begin(self):
+        check(self._lib.ils_profile_begin(self._h), "ils_profile_begin")
+
+    def profile_end(self) -> dict:
+        """{kind: (total_ms, launches)} for the launches since profile_begin."""
+        tot = (ctypes.c_double * 4)()
+        cnt = (ctypes.c_int * 4)()
+        check(self._lib.ils_profile_end(self._h, tot, cnt), "ils_profile_end")
+        return {k: (tot[i], cnt[i]) for i, k in enumerate(self.PASS_KINDS)}
+
+    # -- smoothing ---------------------------------------------------------
+    def smooth(self, f: torch.Tensor, lam: float, p: float, eps: float = 1e-4, N: int = 4,
+               out: torch.Tensor | None = None) -> torch.Tensor:
+        """u^N of Algorithm 1 for a (H, W) or (C, H, W) float32 GPU tensor."""
+        fc = _as_chw(f, "f")
+        out = torch.empty_like(f) if out is None else out
+        oc = _as_chw(out, "out")
+        if oc.shape != fc.shape:
+            raise ValueError("out must have the shape of f")
+        C, H, W = fc.shape
+        self._bind_stream()
+        check(self._lib.ils_smooth(self._h, ctypes.c_void_p(fc.data_ptr()), H, W, C, float(lam), float(p),
+                                   float(eps), int(N), ctypes.c_void_p(oc.data_ptr())), "ils_smooth")
+        return out
+
+    def iterate_from(self, f: torch.Tensor, u0: torch.Tensor, lam: float, p: float, eps: float = 1e-4,
+                     N: int = 1, out: torch.Tensor | None = None) -> torch.Tensor:
+        """N iterations of Eqs. (7)-(9) from u^0 = u0 with data term f."""
+        fc = _as_chw(f, "f")
+        uc = _as_chw(u0, "u0")
+        if uc.shape != fc.shape:
+            raise ValueError("u0 must have the shape of f")
+        out = torch.empty_like(f) if out is None else out
+        oc = _as_chw(out, "out")
+        C, H, W = fc.shape
+        self._bind_stream()
+        check(self._lib.ils_iterate_from(self._h, ctypes.c_void_p(fc.data_ptr()), ctypes.c_void_p(uc.data_ptr()),
+                                         H, W, C, float(lam), float(p), float(eps), int(N),
+                                         ctypes.c_void_p(oc.data_ptr())), "ils_iterate_from")
+        return out
+
+    def smooth_batch(self, frames: Sequence[tuple], outs: Sequence[torch.Tensor] | None = None,
+                     u0s: Sequence[torch.Tensor | None] | None = None) -> list[torch.Tensor]:
+        """frames: sequence of (f, lam, p, eps, N); returns the outputs."""
+        n = len(frames)
+        arr = (IlsFrame * n)()
+        keep = []
+        res = []
+        for i, (f, lam, p, eps, N) in enumerate(frames):
+            fc = _as_chw(f, f"frames[{i}].f")
+            o = torch.empty_like(f) if outs is None else outs[i]
+            oc = _as_chw(o, f"outs[{i}]")
+            u0 = None if u0s is None else u0s[i]
+            uc = None if u0 is None else _as_chw(u0, f"u0s[{i}]")
+            C, H, W = fc.shape
+            arr[i] = IlsFrame(fc.data_ptr(), oc.data_ptr(), H, W, C, float(lam), float(p), float(eps), int(N),
+                              0 if uc is None else uc.data_ptr())
+            keep.append((fc, oc, uc))
+            res.append(o)
+        need = int(self._lib.ils_batch_workspace_bytes(arr, n))
+        if need > self.workspace.numel():
+            raise ValueError(f"batch needs {need} workspace bytes, plan has {self.workspace.numel()}")
+        self._bind_stream()
+        check(self._lib.ils_smooth_batch(self._h, arr, n), "ils_smooth_batch")
+        return res
+
+    def rms_diff(self, a: Sequence[torch.Tensor], b: Sequence[torch.Tensor]) -> torch.Tensor:
+        """Per-pair RMS of (a_i - b_i) as a float32 GPU tensor of length n."""
+        n = len(a)
+        pa = (ctypes.c_void_p * n)(*[t.data_ptr() for t in a])
+        pb = (ctypes.c_void_p * n)(*[t.data_ptr() for t in b])
+        cnt = (ctypes.c_longlong * n)(*[t.numel() for t in a])
+        for x, y in zip(a, b):
+            if x.shape != y.shape or x.dtype != torch.float32 or y.dtype != torch.float32:
+                raise ValueError("rms_diff needs float32 pairs of equal shape")
+            if not (x.is_contiguous() and y.is_contiguous()):
+                raise ValueError("rms_diff needs contiguous tensors")
+        out = torch.empty(n, dtype=torch.float32, device=self.device)
+        self._bind_stream()
+        check(self._lib.ils_rms_diff(self._h, pa, pb, cnt, n, ctypes.c_void_p(out.data_ptr())), "ils_rms_diff")
+        return out
+
+    # -- single passes ----------------------------------------------------
+    def debug_rhs_spectrum(self, f, u0, lam, p, eps=1e-4) -> torch.Tensor:
+        fc = _as_chw(f, "f")
+        uc = _as_chw(u0, "u0")
+        C, H, W = fc.shape
+        spec = torch.empty((C, H, W // 2 + 1), dtype=torch.complex64, device=f.device)
+        self._bind_stream()
+        check(self._lib.ils_debug_rhs_spectrum(self._h, ctypes.c_void_p(fc.data_ptr()), ctypes.c_void_p(uc.data_ptr()),
+                                               H, W, C, float(lam), float(p), float(eps),
+                                               ctypes.c_void_p(spec.data_ptr())), "ils_debug_rhs_spectrum")
+        return spec
+
+    def debug_column_solve(self, spec_in: torch.Tensor, W: int, lam, p, eps=1e-4) -> torch.Tensor:
+        if spec_in.dtype != torch.complex64 or not spec_in.is_contiguous() or spec_in.dim() != 3:
+            raise ValueError("spec_in must be contiguous complex64 (C, H, W/2+1)")
+        C, H, Wh = spec_in.shape
+        if Wh != W // 2 + 1:
+            raise ValueError("spec_in width must be W/2+1")
+        out = torch.empty_like(spec_in)
+        self._bind_stream()
+        check(self._lib.ils_debug_column_solve(self._h, ctypes.c_void_p(spec_in.data_ptr()), H, W, C, float(lam),
+                                               float(p), float(eps), ctypes.c_void_p(out.data_ptr())),
+              "ils_debug_column_solve")
+        return out
+
+    def debug_row_inverse(self, spec: torch.Tensor, W: int) -> torch.Tensor:
+        if spec.dtype != torch.complex64 or not spec.is_contiguous() or spec.dim() != 3:
+            raise ValueError("spec must be contiguous complex64 (C, H, W/2+1)")
+        C, H, Wh = spec.shape
+        out = torch.empty((C, H, W), dtype=torch.float32, device=spec.device)
+        self._bind_stream()
+        check(self._lib.ils_debug_row_inverse(self._h, ctypes.c_void_p(spec.data_ptr()), H, W, C,
+                                              ctypes.c_void_p(out.data_ptr())), "ils_debug_row_inverse")
+        return out
+
+
+_plans: dict = {}
+
+
+def smooth(f: torch.Tensor, lam: float, p: float, eps: float = 1e-4, N: int = 4,
+           out: torch.Tensor | None = None) -> torch.Tensor:
+    """One-call convenience: smooth with a plan cached per (device, size)."""
+    fc = _as_chw(f, "f")
+    C, H, W = fc.shape
+    key = (f.device.index, H, W, C)
+    plan = _plans.get(key)
+    if plan is None:
+        plan = _plans[key] = Plan(H, W, C, 1, device=f.device)
+    return plan.smooth(f, lam, p, eps, N, out)

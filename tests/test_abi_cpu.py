@@ -1,0 +1,131 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/ils.h declares, and rejects invalid arguments before any HIP call."""
+import ctypes
+import math
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ils.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ils_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2003_07504_amd import _lib
+    return _lib.load()
+
+
+def test_header_declares_expected_entry_points():
+    names = _declared()
+    for required in ("ils_plan_create", "ils_smooth", "ils_plan_destroy", "ils_smooth_batch"):
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(L):
+    from paper_2003_07504_amd import _lib
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (ils_[a-z_0-9]+)$", out, flags=re.M))
+    for name in _declared():
+        assert name in exported, name
+        assert name in _lib.SIGNATURES, name
+        getattr(L, name)
+
+
+def test_smooth_signature_order_matches_header():
+    text = open(HEADER).read()
+    m = re.search(r"int ils_smooth\(([^)]*)\)", text)
+    params = [p.split()[-1].lstrip("*") for p in m.group(1).replace("\n", " ").split(",")]
+    assert params == ["plan", "f", "H", "W", "C", "lambda", "p", "eps", "N", "out"]
+
+
+def test_status_strings(L):
+    for code in (0, -1, -2, -3, -4, -5):
+        assert L.ils_status_string(code)
+    assert L.ils_status_string(0) == b"ok"
+
+
+@pytest.mark.parametrize("H,W", [(256, 256), (1080, 1920), (2160, 3840), (480, 640), (720, 1280), (8, 8),
+                                 (16, 16), (90, 120)])
+def test_config_sizes_supported(L, H, W):
+    assert L.ils_size_supported(H, W) == 1
+
+
+@pytest.mark.parametrize("H,W", [(1080, 1921), (7, 8), (1, 8), (8, 1), (1080, 14), (1000, 1920)])
+def test_unsupported_sizes(L, H, W):
+    assert L.ils_size_supported(H, W) == 0
+
+
+def test_compiled_lengths_are_235_smooth(L):
+    for n in range(1, 2200):
+        if L.ils_length_supported(n):
+            m = n
+            for q in (2, 3, 5):
+                while m % q == 0:
+                    m //= q
+            assert m == 1, n
+
+
+@pytest.mark.parametrize("args,code", [
+    ((1080, 1920, 3, 1.0, 0.8, 1e-4, 4), 0),
+    ((1080, 1920, 3, 0.0, 0.8, 1e-4, 4), 0),
+    ((1080, 1920, 3, 1.0, 2.0, 1e-4, 0), 0),
+    ((1080, 1920, 0, 1.0, 0.8, 1e-4, 4), -1),
+    ((1080, 1920, 3, -1.0, 0.8, 1e-4, 4), -1),
+    ((1080, 1920, 3, math.nan, 0.8, 1e-4, 4), -1),
+    ((1080, 1920, 3, math.inf, 0.8, 1e-4, 4), -1),
+    ((1080, 1920, 3, 1.0, 0.0, 1e-4, 4), -1),
+    ((1080, 1920, 3, 1.0, 2.5, 1e-4, 4), -1),
+    ((1080, 1920, 3, 1.0, math.nan, 1e-4, 4), -1),
+    ((1080, 1920, 3, 1.0, 0.8, 0.0, 4), -1),
+    ((1080, 1920, 3, 1.0, 0.8, -1e-4, 4), -1),
+    ((1080, 1920, 3, 1.0, 0.8, 1e-4, -1), -1),
+    ((1, 1920, 3, 1.0, 0.8, 1e-4, 4), -1),
+    ((1080, 1921, 3, 1.0, 0.8, 1e-4, 4), -2),
+    ((1001, 1920, 3, 1.0, 0.8, 1e-4, 4), -2),
+])
+def test_check_args(L, args, code):
+    assert L.ils_check_args(*args) == code
+
+
+def test_null_plan_and_pointers_rejected(L):
+    assert L.ils_smooth(None, None, 8, 8, 1, 1.0, 0.8, 1e-4, 4, None) == -1
+    assert L.ils_iterate_from(None, None, None, 8, 8, 1, 1.0, 0.8, 1e-4, 1, None) == -1
+    assert L.ils_smooth_batch(None, None, 1) == -1
+    assert L.ils_plan_destroy(None) == 0
+    assert L.ils_plan_set_stream(None, None) == -1
+    assert L.ils_last_error(None) == -1
+    assert L.ils_rms_diff(None, None, None, None, 1, None) == -1
+    assert L.ils_debug_rhs_spectrum(None, None, None, 8, 8, 1, 1.0, 0.8, 1e-4, None) == -1
+
+
+def test_plan_create_rejects_bad_arguments_before_hip(L):
+    h = ctypes.c_void_p()
+    assert L.ils_plan_create(None, 8, 8, 1, 1, None, 0, None, 0) == -1
+    assert L.ils_plan_create(ctypes.byref(h), 1, 8, 1, 1, None, 0, None, 0) == -1
+    assert L.ils_plan_create(ctypes.byref(h), 8, 8, 1, 1, None, 1 << 30, None, 0) == -3
+    assert L.ils_plan_create(ctypes.byref(h), 8, 8, 1, 1, ctypes.c_void_p(4096 + 8), 1 << 30, None, 0) == -3
+    assert L.ils_plan_create(ctypes.byref(h), 8, 8, 1, 1, ctypes.c_void_p(4096), 16, None, 0) == -3
+    assert L.ils_plan_create(ctypes.byref(h), 8, 8, 1, 1, ctypes.c_void_p(4096), 1 << 30, None, 7) == -1
+    assert h.value is None
+
+
+def test_workspace_bytes(L):
+    one = L.ils_workspace_bytes(1080, 1920, 3, 1)
+    # two half spectra, rows padded to 976 complex values, plus the 1 MiB header
+    assert one == (1 << 20) + 2 * 3 * 1080 * 976 * 8
+    assert L.ils_workspace_bytes(1080, 1920, 3, 4) == (1 << 20) + 4 * 2 * 3 * 1080 * 976 * 8
+    assert L.ils_workspace_bytes(0, 1920, 3, 1) == 0
+    from paper_2003_07504_amd._lib import IlsFrame
+    arr = (IlsFrame * 2)()
+    arr[0] = IlsFrame(None, None, 480, 640, 1, 1.0, 0.8, 1e-4, 4, None)
+    arr[1] = IlsFrame(None, None, 1080, 1920, 3, 1.0, 0.8, 1e-4, 4, None)
+    assert L.ils_batch_workspace_bytes(arr, 2) == (1 << 20) + 2 * 480 * 336 * 8 + 2 * 3 * 1080 * 976 * 8
