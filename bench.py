@@ -104,7 +104,11 @@ def main():
     from paper_2003_07504_amd import ils
     from synth import voronoi_image
 
+    def say(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
     H, W, C, lam, p, eps, N = 1080, 1920, 3, 1.0, 0.8, 1e-4, 4
+    say(f"generating {args.ring} frames {W}x{H}x{C}")
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     frames_np = [voronoi_image(H, W, C, 400, 0.05, seed=1 + i) for i in range(args.ring)]
@@ -118,8 +122,10 @@ def main():
             j = i % len(ring)
             plan.smooth(ring[j], lam, p, eps, N, out=outs[j])
 
+    say(f"warmup {args.warmup} steps")
     run(0, args.warmup)
     torch.cuda.synchronize()
+    say(f"timed region {args.steps} steps")
     # ---- timed region
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -139,6 +145,7 @@ def main():
     fps = args.steps / elapsed
 
     # ---- per-pass durations (HIP events around every launch, same workload)
+    say("per-pass event timing")
     plan.profile_begin()
     run(args.warmup + args.steps, args.steps)
     prof = plan.profile_end()
@@ -158,6 +165,7 @@ def main():
 
     extras = {}
     if not args.no_extras:
+        say("hot single frame and batched figures")
         # hot: the same frame over and over (working set resident in the last-level cache)
         torch.cuda.synchronize()
         a = time.perf_counter()
@@ -186,6 +194,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
+        say(f"cpu baseline (oracle) for about {args.cpu_seconds} s")
         cpu = cpu_baseline(frames_np, H, W, C, lam, p, eps, N, args.cpu_seconds)
 
     line = {

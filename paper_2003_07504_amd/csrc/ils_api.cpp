@@ -14,7 +14,7 @@
 #include "../../include/ils.h"
 #include "ils_launch.hpp"
 
-using ilsk::BatchList;
+using ilsk::WorkList;
 using ilsk::cf;
 using ilsk::FrameDesc;
 using ilsk::LenOps;
@@ -192,17 +192,42 @@ static void fill_desc(const ils_plan* plan, FrameDesc& d, int H, int W, int C, f
   d.col_scale = (float)(1.0 / (2.0 * (double)H * (double)W));
 }
 
-// Enqueue Algorithm 1 for one frame (N >= 1, lambda > 0).
+// Single-frame work lists for the three launch shapes of a frame.
+static WorkList one_frame(const FrameDesc& d, int items) {
+  WorkList wl;
+  wl.one = d;
+  wl.descs = nullptr;
+  wl.starts = nullptr;
+  wl.n = 1;
+  wl.total = items;
+  return wl;
+}
+static int row_items(const LenOps* o, int mode, const FrameDesc& d) {
+  const int g = o->row_rows[mode];
+  return d.C * ((d.H + g - 1) / g);
+}
+static int col_items(const LenOps* o, const FrameDesc& d) {
+  const int s = o->col_cols;
+  return d.C * ((d.W / 2 + 1 + s - 1) / s);
+}
+
+// Enqueue Algorithm 1 for one frame (N >= 1, lambda > 0): one block per
+// work item, 2N + 1 launches.
 static int run_frame(ils_plan* plan, const FrameDesc& d, int N) {
   const LenOps* orow = find_ops(d.W / 2);
   const LenOps* ocol = find_ops(d.H);
   hipStream_t st = plan->stream;
-  hipError_t e = timed(plan, 0, [&] { return orow->row(ilsk::ROW_FIRST, d, st); });
+  const WorkList wrow = one_frame(d, row_items(orow, ilsk::ROW_MID, d));
+  const WorkList wfin = one_frame(d, row_items(orow, ilsk::ROW_FINAL, d));
+  const WorkList wcol = one_frame(d, col_items(ocol, d));
+  hipError_t e = timed(plan, 0, [&] { return orow->row(ilsk::ROW_FIRST, wrow, st); });
   for (int n = 0; n < N && e == hipSuccess; ++n) {
-    e = timed(plan, 3, [&] { return ocol->col(d, st); });
+    e = timed(plan, 3, [&] { return ocol->col(wcol, st); });
     if (e != hipSuccess) break;
-    const int mode = n + 1 < N ? ilsk::ROW_MID : ilsk::ROW_FINAL;
-    e = timed(plan, mode, [&] { return orow->row(mode, d, st); });
+    if (n + 1 < N)
+      e = timed(plan, 1, [&] { return orow->row(ilsk::ROW_MID, wrow, st); });
+    else
+      e = timed(plan, 2, [&] { return orow->row(ilsk::ROW_FINAL, wfin, st); });
   }
   return record(plan, e);
 }
@@ -498,7 +523,7 @@ int ils_smooth_batch(ils_plan* plan, const ils_frame* frames, int n) {
     const LenOps* orow;
     const LenOps* ocol;
     int N;
-    BatchList row, fin, col;
+    WorkList row, fin, col;
   };
   std::vector<Launch> launches;
   std::vector<size_t> offs;  // (desc, row starts, fin starts, col starts) per class
@@ -523,9 +548,9 @@ int ils_smooth_batch(ils_plan* plan, const ils_frame* frames, int n) {
     offs.push_back(put(sfin.data(), sfin.size() * sizeof(int)));
     offs.push_back(put(scol.data(), scol.size() * sizeof(int)));
     const int nf = (int)cl.idx.size();
-    L.row = BatchList{nullptr, nullptr, nf, srow.back()};
-    L.fin = BatchList{nullptr, nullptr, nf, sfin.back()};
-    L.col = BatchList{nullptr, nullptr, nf, scol.back()};
+    L.row = WorkList{FrameDesc{}, nullptr, nullptr, nf, srow.back()};
+    L.fin = WorkList{FrameDesc{}, nullptr, nullptr, nf, sfin.back()};
+    L.col = WorkList{FrameDesc{}, nullptr, nullptr, nf, scol.back()};
     launches.push_back(L);
   }
   if (hdr.size() > kBatchHeaderBytes) return ILS_ERR_WORKSPACE;
@@ -541,30 +566,26 @@ int ils_smooth_batch(ils_plan* plan, const ils_frame* frames, int n) {
   hipError_t e = stage_upload(plan, plan->ws, hdr.data(), hdr.size());
   if (e != hipSuccess) return record(plan, e);
 
-  // Persistent grid: enough blocks to fill every CU a few times over.
-  int cus = 256;
-  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, plan->device);
-  auto grid_for = [&](int total) { return total < 8 * cus ? total : 8 * cus; };
   int maxN = 0;
   for (const Launch& L : launches) maxN = L.N > maxN ? L.N : maxN;
   // Pass-major order: every class's pass k is enqueued before any pass k+1.
   hipStream_t st = plan->stream;
   for (const Launch& L : launches) {
-    e = timed(plan, 0, [&] { return L.orow->row_batch(ilsk::ROW_FIRST, L.row, grid_for(L.row.total), st); });
+    e = timed(plan, 0, [&] { return L.orow->row(ilsk::ROW_FIRST, L.row, st); });
     if (e != hipSuccess) return record(plan, e);
   }
   for (int n = 0; n < maxN; ++n) {
     for (const Launch& L : launches) {
       if (n >= L.N) continue;
-      e = timed(plan, 3, [&] { return L.ocol->col_batch(L.col, grid_for(L.col.total), st); });
+      e = timed(plan, 3, [&] { return L.ocol->col(L.col, st); });
       if (e != hipSuccess) return record(plan, e);
     }
     for (const Launch& L : launches) {
       if (n >= L.N) continue;
       if (n + 1 < L.N)
-        e = timed(plan, 1, [&] { return L.orow->row_batch(ilsk::ROW_MID, L.row, grid_for(L.row.total), st); });
+        e = timed(plan, 1, [&] { return L.orow->row(ilsk::ROW_MID, L.row, st); });
       else
-        e = timed(plan, 2, [&] { return L.orow->row_batch(ilsk::ROW_FINAL, L.fin, grid_for(L.fin.total), st); });
+        e = timed(plan, 2, [&] { return L.orow->row(ilsk::ROW_FINAL, L.fin, st); });
       if (e != hipSuccess) return record(plan, e);
     }
   }
@@ -587,7 +608,8 @@ int ils_debug_rhs_spectrum(ils_plan* plan, const float* f, const float* u0, int 
   char* base = plan->ws + kBatchHeaderBytes;
   d.specA = reinterpret_cast<cf*>(base);
   d.specB = reinterpret_cast<cf*>(base + (size_t)C * H * d.ldS * sizeof(cf));
-  hipError_t e = find_ops(W / 2)->row(ilsk::ROW_FIRST, d, plan->stream);
+  const LenOps* o = find_ops(W / 2);
+  hipError_t e = o->row(ilsk::ROW_FIRST, one_frame(d, row_items(o, ilsk::ROW_FIRST, d)), plan->stream);
   if (e == hipSuccess)
     e = hipMemcpy2DAsync(spec, (size_t)(W / 2 + 1) * sizeof(cf), d.specA, (size_t)d.ldS * sizeof(cf),
                          (size_t)(W / 2 + 1) * sizeof(cf), (size_t)C * H, hipMemcpyDeviceToDevice,
@@ -612,7 +634,8 @@ int ils_debug_column_solve(ils_plan* plan, const float* spec_in, int H, int W, i
   const size_t rowb = (size_t)(W / 2 + 1) * sizeof(cf);
   hipError_t e = hipMemcpy2DAsync(d.specA, (size_t)d.ldS * sizeof(cf), spec_in, rowb, rowb,
                                   (size_t)C * H, hipMemcpyDeviceToDevice, plan->stream);
-  if (e == hipSuccess) e = find_ops(H)->col(d, plan->stream);
+  const LenOps* oc = find_ops(H);
+  if (e == hipSuccess) e = oc->col(one_frame(d, col_items(oc, d)), plan->stream);
   if (e == hipSuccess)
     e = hipMemcpy2DAsync(spec_out, rowb, d.specB, (size_t)d.ldS * sizeof(cf), rowb, (size_t)C * H,
                          hipMemcpyDeviceToDevice, plan->stream);
@@ -634,7 +657,8 @@ int ils_debug_row_inverse(ils_plan* plan, const float* spec, int H, int W, int C
   const size_t rowb = (size_t)(W / 2 + 1) * sizeof(cf);
   hipError_t e = hipMemcpy2DAsync(d.specB, (size_t)d.ldS * sizeof(cf), spec, rowb, rowb, (size_t)C * H,
                                   hipMemcpyDeviceToDevice, plan->stream);
-  if (e == hipSuccess) e = find_ops(W / 2)->row(ilsk::ROW_FINAL, d, plan->stream);
+  const LenOps* o = find_ops(W / 2);
+  if (e == hipSuccess) e = o->row(ilsk::ROW_FINAL, one_frame(d, row_items(o, ilsk::ROW_FINAL, d)), plan->stream);
   return record(plan, e);
 }
 

@@ -40,17 +40,20 @@ __device__ __forceinline__ float mu_ns(float g, float a_exp, float inv_eps) {
 template <int P, int Q>
 struct RowGeom {
   static constexpr int M = P * Q;
-  static constexpr int T = P > Q ? P : Q;  // lanes per row slot
-  static constexpr int QP = Q | 1;         // padded exchange row (odd => conflict-free)
+  static constexpr int T = P > Q ? P : Q;    // lanes per row slot
+  static constexpr int QP = Q | 1;           // padded exchange row (odd => conflict-free)
   static constexpr int SLOT_F = 2 * P * QP;  // floats of LDS per row slot (>= W)
+  static constexpr int TAB_F = 2 * M;        // twiddle table exp(-2 pi i j / M), j < M
+  static constexpr int NPOST = (M + 1 + T - 1) / T;  // post-process elements per lane
 };
 
 // Rows per row-pass workgroup: two workgroups per CU when the LDS allows it.
 template <int P, int Q>
 constexpr int row_band() {
-  constexpr int bytes = 4 * RowGeom<P, Q>::SLOT_F;
-  int g = 76000 / bytes - 2;
-  if (g < 4) g = 150000 / bytes - 2;
+  constexpr int slot = 4 * RowGeom<P, Q>::SLOT_F;
+  constexpr int tab = 4 * RowGeom<P, Q>::TAB_F;
+  int g = (78000 - tab) / slot - 2;
+  if (g < 4) g = (155000 - tab) / slot - 2;
   if (g > 14) g = 14;
   if (g < 1) g = 1;
   return g;
@@ -60,21 +63,95 @@ template <int P, int Q>
 struct ColGeom {
   static constexpr int H = P * Q;
   static constexpr int T = P > Q ? P : Q;
+  static constexpr int TAB_F = 2 * H;  // twiddles exp(-2 pi i j / H)
   static constexpr int pick_s() {
-    if (P * Q * 16 * 8 <= 40000) return 16;
-    if (P * (Q * 8 + 8) * 8 <= 80000) return 8;
+    if (2 * P * Q * 16 * 4 + 4 * TAB_F <= 40000) return 16;
+    if (2 * P * (Q * 8 + 8) * 4 + 4 * TAB_F <= 80000) return 8;
     return 4;
   }
   static constexpr int S = pick_s();
   // stride between k1 blocks of the exchange (in complex elements), padded so
   // that successive k1 groups land on different LDS banks
   static constexpr int KS = (S >= 16) ? Q * S : Q * S + ((S - (Q * S) % 16) + 16) % 16;
-  static constexpr int LDS_F = 2 * P * KS;
+  static constexpr int EX_F = 2 * P * KS;
+  static constexpr int LDS_F = EX_F + TAB_F;
 };
+
+// exp(+- i pi m / n) as a compile-time complex constant.
+template <long long m, long long n>
+__device__ __forceinline__ cf turn_half() {
+  constexpr dcs w = cossin_turn(m, 2 * n);
+  return cf{float(w.c), float(w.s)};
+}
+
+// ---- C2R stage A' of one row (lane k1 < P): pre-process X[k], X[M-k] into
+// Z[k] = (X[k] + conj X[M-k]) + i (X[k] - conj X[M-k]) exp(i pi k / M),
+// Q-point inverse DFT over k2 (k = k1 + P k2), twiddle exp(2 pi i t k1 / M),
+// write the exchange row [k1][t].
+template <int P, int Q>
+__device__ __forceinline__ void c2r_stage_a(const cf* X, int k1, cf w1, const cf* tws, cf* slc) {
+  constexpr int M = P * Q, QP = Q | 1;
+  cf v[Q];
+  static_for<Q>([&](auto k2c) {
+    constexpr int k2 = decltype(k2c)::value;
+    const int k = k1 + P * k2;
+    cf a = X[k];
+    cf b = X[M - k];
+    if (k2 == 0 && k1 == 0) {  // DC and Nyquist bins: real parts only
+      a.y = 0.0f;
+      b.y = 0.0f;
+    }
+    const cf bc = {b.x, -b.y};
+    const cf e = cadd(a, bc);
+    // exp(i pi k / M) = exp(i pi k1 / M) exp(i pi k2 / Q)
+    const cf wk = (k2 == 0) ? w1 : cmul(w1, turn_half<k2, Q>());
+    const cf o = cmul(csub(a, bc), wk);
+    v[k2] = {e.x - o.y, e.y + o.x};  // e + i o
+  });
+  dft<Q, +1>(v);
+  static_for<Q>([&](auto tc) {
+    constexpr int t = decltype(tc)::value;
+    slc[k1 * QP + t] = (t == 0) ? v[t] : cmulc(v[t], tws[t * k1]);
+  });
+}
+
+// ---- C2R stage B' (lane t < Q): P-point inverse DFT over k1 -> z[Q n1 + t].
+template <int P, int Q>
+__device__ __forceinline__ void c2r_stage_b(const cf* slc, int t, cf (&z)[P]) {
+  constexpr int QP = Q | 1;
+  static_for<P>([&](auto k1c) {
+    constexpr int k1 = decltype(k1c)::value;
+    z[k1] = slc[k1 * QP + t];
+  });
+  dft<P, +1>(z);
+}
+
+// ---- R2C post-process of one row held in LDS in natural order Z[0..M-1]:
+// X'[k] = E - i W_2M^k D with E = Z[k] + conj Z[M-k], D = Z[k] - conj Z[M-k]
+// (X' = 2 X), k = lane + T i <= M;  W_2M^k = W_2M^lane * W_2M^(T i).
+template <int P, int Q>
+__device__ __forceinline__ void r2c_post(const cf* slc, int lane, cf wl, cf* Xo) {
+  using Geo = RowGeom<P, Q>;
+  constexpr int M = Geo::M, T = Geo::T;
+  static_for<Geo::NPOST>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    const int k = lane + T * i;
+    if (k <= M) {
+      cf A = slc[k == M ? 0 : k];
+      cf B = slc[k == 0 ? 0 : M - k];
+      B.y = -B.y;
+      const cf E = cadd(A, B), D = csub(A, B);
+      const cf w = (i == 0) ? wl : cmul(wl, turn_half<-(long long)T * i, M>());
+      const cf wD = cmul(D, w);
+      Xo[k] = {E.x + wD.y, E.y - wD.x};  // E - i wD
+    }
+  });
+}
 
 // --------------------------------------------------------------------------
 // Row pass, modes FIRST and MID.  Block = (G + 2) slots x T lanes.
 // Slot s holds row y0 - 1 + s (periodic), s = 0 .. Gv + 1.
+// LDS: (G + 2) slots of SLOT_F floats, then the twiddle table.
 // --------------------------------------------------------------------------
 template <int P, int Q, int G, int MODE>
 __device__ __forceinline__ void row_body(const FrameDesc& d, int band, int ch, float* smem) {
@@ -90,14 +167,21 @@ __device__ __forceinline__ void row_body(const FrameDesc& d, int band, int ch, f
   const int lane = tid - slot * T;
   float* sl = smem + slot * SLOT_F;
   cf* slc = reinterpret_cast<cf*>(sl);
+  cf* tws = reinterpret_cast<cf*>(smem + (G + 2) * SLOT_F);
   const bool in_slot = slot <= Gv + 1;
   int yrow = y0 - 1 + slot;
   yrow = yrow < 0 ? yrow + H : (yrow >= H ? yrow - H : yrow);
   if (!in_slot) yrow = 0;
+  const bool out_slot = slot >= 1 && slot <= Gv;
+  const int yout = out_slot ? y0 - 1 + slot : 0;
+  const float2* frow = reinterpret_cast<const float2*>(d.f + (size_t)ch * H * W + (size_t)yout * W);
 
-  const cf* tw = d.tw_row;
-  const cf* tw2 = d.tw2_row;
+  // per-lane factors of the real-FFT twiddles (one load each, issued first)
+  const cf w2lane = d.tw2_row[lane];  // exp(-i pi lane / M)
+  // twiddle table -> LDS
+  for (int i = tid; i < M; i += blockDim.x) tws[i] = d.tw_row[i];
 
+  float2 fv[P];
   if constexpr (MODE == ROW_FIRST) {
     const float* u0 = d.u0 + (size_t)ch * H * W;
     for (int i = tid; i < (Gv + 2) * M; i += blockDim.x) {
@@ -107,65 +191,47 @@ __device__ __forceinline__ void row_body(const FrameDesc& d, int band, int ch, f
       float2 v = *reinterpret_cast<const float2*>(u0 + (size_t)yy * W + 2 * j);
       reinterpret_cast<float2*>(smem + s * SLOT_F)[j] = v;
     }
-  } else {
-    // ---- C2R of this slot's row: pre-process + stage A' (Q-point inverse)
-    if (in_slot && lane < P) {
-      const int k1 = lane;
-      const cf* X = d.specB + (size_t)ch * H * ldS + (size_t)yrow * ldS;
-      cf v[Q];
-      static_for<Q>([&](auto k2c) {
-        constexpr int k2 = decltype(k2c)::value;
-        const int k = k1 + P * k2;
-        cf a = X[k];
-        cf b = X[M - k];
-        if (k2 == 0 && k1 == 0) {  // DC and Nyquist bins: real parts only
-          a.y = 0.0f;
-          b.y = 0.0f;
-        }
-        cf bc = {b.x, -b.y};
-        cf e = cadd(a, bc);
-        cf o = cmulc(csub(a, bc), tw2[k]);  // (X[k] - conj X[M-k]) exp(+i pi k / M)
-        v[k2] = {e.x - o.y, e.y + o.x};    // e + i o
+    if (out_slot && lane < Q) {
+      static_for<P>([&](auto n1c) {
+        constexpr int n1 = decltype(n1c)::value;
+        fv[n1] = frow[Q * n1 + lane];
       });
-      dft<Q, +1>(v);
-      static_for<Q>([&](auto tc) {
-        constexpr int t = decltype(tc)::value;
-        cf w = (t == 0 || k1 == 0) ? cf{1.0f, 0.0f} : tw[t * k1];
-        slc[k1 * QP + t] = cmulc(v[t], w);
+    }
+    __syncthreads();
+  } else {
+    __syncthreads();  // twiddle table ready
+    // ---- C2R of this slot's row
+    if (in_slot && lane < P) {
+      const cf* X = d.specB + (size_t)ch * H * ldS + (size_t)yrow * ldS;
+      c2r_stage_a<P, Q>(X, lane, cf{w2lane.x, -w2lane.y}, tws, slc);
+    }
+    if (out_slot && lane < Q) {  // data term, in flight during the exchange
+      static_for<P>([&](auto n1c) {
+        constexpr int n1 = decltype(n1c)::value;
+        fv[n1] = frow[Q * n1 + lane];
       });
     }
     __syncthreads();
     cf z[P];
-    if (in_slot && lane < Q) {
-      const int t = lane;
-      static_for<P>([&](auto k1c) {
-        constexpr int k1 = decltype(k1c)::value;
-        z[k1] = slc[k1 * QP + t];
-      });
-      dft<P, +1>(z);
-    }
+    if (in_slot && lane < Q) c2r_stage_b<P, Q>(slc, lane, z);
     __syncthreads();
     if (in_slot && lane < Q) {
-      const int t = lane;
       float2* u2 = reinterpret_cast<float2*>(sl);
       static_for<P>([&](auto n1c) {
         constexpr int n1 = decltype(n1c)::value;
-        u2[Q * n1 + t] = make_float2(z[n1].x, z[n1].y);
+        u2[Q * n1 + lane] = make_float2(z[n1].x, z[n1].y);
       });
     }
+    __syncthreads();
   }
-  __syncthreads();
 
   // ---- stencil + stage A (P-point forward) for output slots 1..Gv
-  const bool out_slot = slot >= 1 && slot <= Gv;
-  const int yout = y0 - 1 + slot;
   cf r[P];
   if (out_slot && lane < Q) {
     const int t = lane;
     const float2* uc = reinterpret_cast<const float2*>(sl);
     const float2* uu = reinterpret_cast<const float2*>(sl - SLOT_F);
     const float2* ud = reinterpret_cast<const float2*>(sl + SLOT_F);
-    const float2* frow = reinterpret_cast<const float2*>(d.f + (size_t)ch * H * W + (size_t)yout * W);
     const float a_exp = d.a_exp, inv_eps = d.inv_eps, kappa = d.kappa;
     static_for<P>([&](auto n1c) {
       constexpr int n1 = decltype(n1c)::value;
@@ -182,21 +248,19 @@ __device__ __forceinline__ void row_body(const FrameDesc& d, int band, int ch, f
       float myd1 = mu_ns(dn.y - c.y, a_exp, inv_eps);
       float d0 = (mxl - mx0) + (myu0 - myd0);
       float d1 = (mx0 - mx1) + (myu1 - myd1);
-      float2 fv = frow[j];
-      r[n1] = {fmaf(kappa, d0, fv.x), fmaf(kappa, d1, fv.y)};
+      r[n1] = {fmaf(kappa, d0, fv[n1].x), fmaf(kappa, d1, fv[n1].y)};
     });
     dft<P, -1>(r);
     static_for<P>([&](auto k1c) {
       constexpr int k1 = decltype(k1c)::value;
-      if (k1 != 0 && t != 0) r[k1] = cmul(r[k1], tw[t * k1]);
+      if (k1 != 0) r[k1] = cmul(r[k1], tws[t * k1]);
     });
   }
   __syncthreads();
   if (out_slot && lane < Q) {
-    const int t = lane;
     static_for<P>([&](auto k1c) {
       constexpr int k1 = decltype(k1c)::value;
-      slc[k1 * QP + t] = r[k1];
+      slc[k1 * QP + lane] = r[k1];
     });
   }
   __syncthreads();
@@ -218,18 +282,7 @@ __device__ __forceinline__ void row_body(const FrameDesc& d, int band, int ch, f
     });
   }
   __syncthreads();
-  // ---- R2C post-process: X'[k] = E - i W_2M^k D  (= 2 X[k]),  k = 0..M
-  if (out_slot) {
-    cf* Xo = d.specA + (size_t)ch * H * ldS + (size_t)yout * ldS;
-    for (int k = lane; k <= M; k += T) {
-      cf A = slc[k == M ? 0 : k];
-      cf B = slc[k == 0 ? 0 : M - k];
-      B.y = -B.y;
-      cf E = cadd(A, B), D = csub(A, B);
-      cf wD = cmul(D, tw2[k]);
-      Xo[k] = {E.x + wD.y, E.y - wD.x};  // E - i wD
-    }
-  }
+  if (out_slot) r2c_post<P, Q>(slc, lane, w2lane, d.specA + (size_t)ch * H * ldS + (size_t)yout * ldS);
 }
 
 // --------------------------------------------------------------------------
@@ -239,7 +292,7 @@ __device__ __forceinline__ void row_body(const FrameDesc& d, int band, int ch, f
 template <int P, int Q, int G>
 __device__ __forceinline__ void row_final_body(const FrameDesc& d, int band, int ch, float* smem) {
   using Geo = RowGeom<P, Q>;
-  constexpr int M = Geo::M, T = Geo::T, QP = Geo::QP, SLOT_F = Geo::SLOT_F;
+  constexpr int M = Geo::M, T = Geo::T, SLOT_F = Geo::SLOT_F;
   const int H = d.H;
   const int W = 2 * M;
   const int ldS = d.ldS;
@@ -249,55 +302,34 @@ __device__ __forceinline__ void row_final_body(const FrameDesc& d, int band, int
   const int slot = tid / T;
   const int lane = tid - slot * T;
   cf* slc = reinterpret_cast<cf*>(smem + slot * SLOT_F);
+  cf* tws = reinterpret_cast<cf*>(smem + G * SLOT_F);
   const bool in_slot = slot < Gv;
   const int yrow = in_slot ? y0 + slot : 0;
-  const cf* tw = d.tw_row;
-  const cf* tw2 = d.tw2_row;
-
+  const cf w2lane = d.tw2_row[lane];
+  for (int i = tid; i < M; i += blockDim.x) tws[i] = d.tw_row[i];
+  __syncthreads();
   if (in_slot && lane < P) {
-    const int k1 = lane;
     const cf* X = d.specB + (size_t)ch * H * ldS + (size_t)yrow * ldS;
-    cf v[Q];
-    static_for<Q>([&](auto k2c) {
-      constexpr int k2 = decltype(k2c)::value;
-      const int k = k1 + P * k2;
-      cf a = X[k];
-      cf b = X[M - k];
-      if (k2 == 0 && k1 == 0) {
-        a.y = 0.0f;
-        b.y = 0.0f;
-      }
-      cf bc = {b.x, -b.y};
-      cf e = cadd(a, bc);
-      cf o = cmulc(csub(a, bc), tw2[k]);
-      v[k2] = {e.x - o.y, e.y + o.x};
-    });
-    dft<Q, +1>(v);
-    static_for<Q>([&](auto tc) {
-      constexpr int t = decltype(tc)::value;
-      cf w = (t == 0 || k1 == 0) ? cf{1.0f, 0.0f} : tw[t * k1];
-      slc[k1 * QP + t] = cmulc(v[t], w);
-    });
+    c2r_stage_a<P, Q>(X, lane, cf{w2lane.x, -w2lane.y}, tws, slc);
   }
   __syncthreads();
   if (in_slot && lane < Q) {
-    const int t = lane;
     cf z[P];
-    static_for<P>([&](auto k1c) {
-      constexpr int k1 = decltype(k1c)::value;
-      z[k1] = slc[k1 * QP + t];
-    });
-    dft<P, +1>(z);
+    c2r_stage_b<P, Q>(slc, lane, z);
     float2* orow = reinterpret_cast<float2*>(d.out + (size_t)ch * H * W + (size_t)yrow * W);
     static_for<P>([&](auto n1c) {
       constexpr int n1 = decltype(n1c)::value;
-      orow[Q * n1 + t] = make_float2(z[n1].x, z[n1].y);
+      orow[Q * n1 + lane] = make_float2(z[n1].x, z[n1].y);
     });
   }
 }
 
 // --------------------------------------------------------------------------
 // Column pass.  Block = S columns x T lanes, lane id = s + S * j.
+// LDS: exchange (P x KS complex), twiddles (H complex).  The column
+// eigenvalue 4 sin^2(pi l / H) = (1 - cos t)^2 + sin^2 t, t = 2 pi l / H, is
+// formed from the twiddle table (the squared term keeps full relative
+// precision at small l, where the other is negligible).
 // --------------------------------------------------------------------------
 template <int P, int Q>
 __device__ __forceinline__ void col_body(const FrameDesc& d, int tile, int ch, float* smem) {
@@ -314,19 +346,23 @@ __device__ __forceinline__ void col_body(const FrameDesc& d, int tile, int ch, f
   const cf* in = d.specA + (size_t)ch * H * ldS + cc;
   cf* out = d.specB + (size_t)ch * H * ldS + cc;
   cf* ex = reinterpret_cast<cf*>(smem);
-  const cf* tw = d.tw_col;
+  cf* tws = reinterpret_cast<cf*>(smem + Geo::EX_F);
 
-  if (j < Q) {  // stage A: lane n2 = j, rows Q n1 + n2
-    cf x[P];
+  cf x[P];
+  if (j < Q) {  // stage A loads first: lane n2 = j, rows Q n1 + n2
     static_for<P>([&](auto n1c) {
       constexpr int n1 = decltype(n1c)::value;
       x[n1] = col_ok ? in[(size_t)(Q * n1 + j) * ldS] : cf{0.0f, 0.0f};
     });
+  }
+  const float sxk = d.sx[cc];
+  for (int i = tid; i < H; i += blockDim.x) tws[i] = d.tw_col[i];
+  __syncthreads();
+  if (j < Q) {
     dft<P, -1>(x);
     static_for<P>([&](auto k1c) {
       constexpr int k1 = decltype(k1c)::value;
-      cf v = (k1 == 0 || j == 0) ? x[k1] : cmul(x[k1], tw[j * k1]);
-      ex[k1 * KS + j * S + s] = v;
+      ex[k1 * KS + j * S + s] = (k1 == 0) ? x[k1] : cmul(x[k1], tws[j * k1]);
     });
   }
   __syncthreads();
@@ -337,24 +373,23 @@ __device__ __forceinline__ void col_body(const FrameDesc& d, int tile, int ch, f
       y[n2] = ex[j * KS + n2 * S + s];
     });
     dft<Q, -1>(y);
-    const float sxk = d.sx[cc];
     const float kappa = d.kappa, scale = d.col_scale;
+    const float ksx = fmaf(kappa, sxk, 1.0f);
     static_for<Q>([&](auto k2c) {
       constexpr int k2 = decltype(k2c)::value;
-      float den = fmaf(kappa, sxk + d.sy[j + P * k2], 1.0f);
-      float fac = scale * __builtin_amdgcn_rcpf(den);
-      y[k2] = cscale(y[k2], fac);
+      const cf w = tws[j + P * k2];
+      const float omc = 1.0f - w.x;
+      const float den = fmaf(kappa, fmaf(omc, omc, w.y * w.y), ksx);
+      y[k2] = cscale(y[k2], scale * __builtin_amdgcn_rcpf(den));
     });
     dft<Q, +1>(y);
     static_for<Q>([&](auto n2c) {
       constexpr int n2 = decltype(n2c)::value;
-      cf v = (n2 == 0 || j == 0) ? y[n2] : cmulc(y[n2], tw[n2 * j]);
-      ex[j * KS + n2 * S + s] = v;  // same slots this lane just read
+      ex[j * KS + n2 * S + s] = (n2 == 0) ? y[n2] : cmulc(y[n2], tws[n2 * j]);  // slots this lane read
     });
   }
   __syncthreads();
   if (j < Q) {  // stage B': lane n2 = j, P-point inverse over k1
-    cf x[P];
     static_for<P>([&](auto k1c) {
       constexpr int k1 = decltype(k1c)::value;
       x[k1] = ex[k1 * KS + j * S + s];
