@@ -1,0 +1,613 @@
+// Learned surrogate of the ILS output: training and inference kernels plus
+// the C ABI declared in include/ils_net.h, and the residual-gated inference
+// that falls back to plain ILS.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/ils.h"
+#include "../../include/ils_net.h"
+#include "net_kernels.hpp"
+
+using namespace ilsn;
+
+namespace {
+
+// ---------------------------------------------------------------- network
+struct Layer {
+  int ci, co;    // real channels
+  int cip, cop;  // padded channels of the forward convolution
+  int w_off, b_off;  // offsets (floats) in the master parameter array
+};
+
+// Layer i: 5 -> 32, four times 32 -> 32, 32 -> 3.  Parameters are stored
+// layer by layer as w[co][ci][3][3] followed by b[co].
+__host__ __device__ constexpr Layer layer_def(int i) {
+  int off = 0;
+  Layer L{0, 0, 0, 0, 0, 0};
+  for (int k = 0; k <= i; ++k) {
+    const int ci = (k == 0) ? 5 : 32, co = (k == 5) ? 3 : 32;
+    L = Layer{ci, co, ci == 5 ? 8 : 32, co == 3 ? 16 : 32, off, off + co * ci * 9};
+    off += co * ci * 9 + co;
+  }
+  return L;
+}
+
+struct Net {
+  Layer L[6];
+  size_t nparams;
+  Net() {
+    for (int i = 0; i < 6; ++i) L[i] = layer_def(i);
+    nparams = (size_t)L[5].b_off + L[5].co;
+  }
+};
+const Net kNet;
+
+// channels of the gradient tensor flowing into the output of layer i
+inline int gchan(int i) { return kNet.L[i].co == 3 ? 8 : 32; }
+
+inline size_t al(size_t v) { return (v + 255) / 256 * 256; }
+
+constexpr int kWgradBlocks = 256;
+constexpr int kLossBlocks = 256;
+
+// --------------------------------------------------------- small kernels
+__global__ void __launch_bounds__(256) k_pack_input(const float* f, const float* lam, const float* p, bf16* x0,
+                                                   int B, int H, int W) {
+  const size_t plane = (size_t)H * W;
+  const size_t n = (size_t)B * plane;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+    const size_t img = i / plane, pix = i - img * plane;
+    const float* fi = f + img * 3 * plane + pix;
+    bf16 o[8];
+    o[0] = f2bf(fi[0]);
+    o[1] = f2bf(fi[plane]);
+    o[2] = f2bf(fi[2 * plane]);
+    o[3] = f2bf(lam[img]);
+    o[4] = f2bf(p[img]);
+    o[5] = o[6] = o[7] = f2bf(0.0f);
+    *reinterpret_cast<uint4*>(&x0[i * 8]) = *reinterpret_cast<const uint4*>(o);
+  }
+}
+
+// g6 = d(mean squared error)/dv = 2 (v - t) / n, NHWC bf16 (8 channels);
+// per-block partial sums of (v - t)^2 in double.
+__global__ void __launch_bounds__(256) k_loss_grad(const float* v, const float* t, bf16* g, double* partial,
+                                                  int B, int H, int W) {
+  const size_t plane = (size_t)H * W;
+  const size_t n = (size_t)B * plane;
+  const float scale = (float)(2.0 / (3.0 * (double)n));
+  double acc = 0.0;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+    const size_t img = i / plane, pix = i - img * plane;
+    const size_t base = img * 3 * plane + pix;
+    bf16 o[8];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float d = v[base + c * plane] - t[base + c * plane];
+      acc += (double)d * d;
+      o[c] = f2bf(scale * d);
+    }
+    o[3] = o[4] = o[5] = o[6] = o[7] = f2bf(0.0f);
+    *reinterpret_cast<uint4*>(&g[i * 8]) = *reinterpret_cast<const uint4*>(o);
+  }
+  __shared__ double red[256];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void k_loss_final(const double* partial, int nb, double n, float* loss) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < nb; ++i) s += partial[i];
+    *loss = (float)(s / n);
+  }
+}
+
+// Partial weight and bias gradients of one convolution (fp32 VALU):
+//   dW[co][ci][tap] = sum_pixels g[pixel][co] x[pixel + shift(tap)][ci],  db[co] = sum g[pixel][co]
+// Thread (co pair, ci pair) keeps 2 x 2 x 9 accumulators; blocks stride over
+// TH x TW pixel tiles and write one partial row each (reduced in a fixed order
+// afterwards, so the result is deterministic).
+template <int GC, int XC>
+__global__ void __launch_bounds__(256) k_wgrad(const bf16* g, const bf16* x, float* partial, int gcr, int xcr,
+                                              int B, int H, int W) {
+  constexpr int LH = TH + 2, LW = TW + 2;
+  __shared__ __attribute__((aligned(16))) bf16 gt[TH * TW * GC];
+  __shared__ __attribute__((aligned(16))) bf16 xt[LH * LW * XC];
+  constexpr int NI2 = XC / 2;
+  const int tid = threadIdx.x;
+  const bool active = tid < (GC / 2) * NI2;
+  const int cp = tid / NI2, ip = tid - (tid / NI2) * NI2;
+  const int co0 = 2 * cp, ci0 = 2 * ip;
+  float acc[2][2][9];
+  float accb[2] = {0.f, 0.f};
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int k = 0; k < 9; ++k) acc[i][j][k] = 0.f;
+
+  const int tiles_x = (W + TW - 1) / TW, tiles_y = (H + TH - 1) / TH;
+  const int ntiles = B * tiles_x * tiles_y;
+  const size_t plane = (size_t)H * W;
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int img = tile / (tiles_x * tiles_y);
+    const int rem = tile - img * tiles_x * tiles_y;
+    const int ty = rem / tiles_x, tx = rem - ty * tiles_x;
+    const int y0 = ty * TH, x0 = tx * TW;
+    for (int i = tid; i < TH * TW * (GC / 8); i += 256) {
+      const int pix = i / (GC / 8), chn = i - pix * (GC / 8);
+      const int py = pix / TW, px = pix - py * TW;
+      const int gy = y0 + py, gx = x0 + px;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (gy < H && gx < W) v = *reinterpret_cast<const uint4*>(&g[((size_t)img * plane + (size_t)gy * W + gx) * GC + chn * 8]);
+      *reinterpret_cast<uint4*>(&gt[pix * GC + chn * 8]) = v;
+    }
+    for (int i = tid; i < LH * LW * (XC / 8); i += 256) {
+      const int pix = i / (XC / 8), chn = i - pix * (XC / 8);
+      const int ly = pix / LW, lx = pix - ly * LW;
+      const int gy = wrapi(y0 + ly - 1, H), gx = wrapi(x0 + lx - 1, W);
+      *reinterpret_cast<uint4*>(&xt[pix * XC + chn * 8]) =
+          *reinterpret_cast<const uint4*>(&x[((size_t)img * plane + (size_t)gy * W + gx) * XC + chn * 8]);
+    }
+    __syncthreads();
+    if (active) {
+      for (int py = 0; py < TH; ++py) {
+        for (int px = 0; px < TW; ++px) {
+          const int gi = (py * TW + px) * GC + co0;
+          const float g0 = bf2f(gt[gi]), g1 = bf2f(gt[gi + 1]);
+          accb[0] += g0;
+          accb[1] += g1;
+#pragma unroll
+          for (int ta = 0; ta < 3; ++ta) {
+#pragma unroll
+            for (int tc = 0; tc < 3; ++tc) {
+              const int xi = ((py + ta) * LW + px + tc) * XC + ci0;
+              const float x0v = bf2f(xt[xi]), x1v = bf2f(xt[xi + 1]);
+              const int tap = ta * 3 + tc;
+              acc[0][0][tap] = fmaf(g0, x0v, acc[0][0][tap]);
+              acc[0][1][tap] = fmaf(g0, x1v, acc[0][1][tap]);
+              acc[1][0][tap] = fmaf(g1, x0v, acc[1][0][tap]);
+              acc[1][1][tap] = fmaf(g1, x1v, acc[1][1][tap]);
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (!active) return;
+  float* out = partial + (size_t)blockIdx.x * (size_t)(gcr * xcr * 9 + gcr);
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int co = co0 + i;
+    if (co >= gcr) continue;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int ci = ci0 + j;
+      if (ci >= xcr) continue;
+#pragma unroll
+      for (int tap = 0; tap < 9; ++tap) out[((size_t)co * xcr + ci) * 9 + tap] = acc[i][j][tap];
+    }
+    if (ip == 0) out[(size_t)gcr * xcr * 9 + co] = accb[i];
+  }
+}
+
+// grad[k] = sum over blocks (fixed order) of partial[b][k]
+__global__ void __launch_bounds__(256) k_reduce_partials(const float* partial, int nblocks, int len, float* grad) {
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k >= len) return;
+  double s = 0.0;
+  for (int b = 0; b < nblocks; ++b) s += partial[(size_t)b * len + k];
+  grad[k] = (float)s;
+}
+
+// Adam with bias correction (Kingma & Ba): fp32 master parameters.
+__global__ void __launch_bounds__(256) k_adam(float* prm, float* m, float* v, const float* g, int n, float lr,
+                                             float b1, float b2, float eps, float c1, float c2) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float mhat = mi / c1, vhat = vi / c2;
+  prm[i] -= lr * mhat / (sqrtf(vhat) + eps);
+}
+
+// Pack master fp32 weights into the bf16 fragment layouts.
+//   forward WF[co][tap*CIP + ci]    = w[co][ci][tap]
+//   dgrad   WD[ci][tap'*COPg + co]  = w[co][ci][8 - tap']   (flipped, transposed)
+// and the padded fp32 biases.
+struct PackArgs {
+  const float* master;
+  bf16* wf[6];
+  bf16* wd[6];
+  float* bias[6];
+};
+
+__global__ void __launch_bounds__(256) k_pack_weights(PackArgs a) {
+  const int layer = blockIdx.y;
+  const Layer L = layer_def(layer);
+  const float* w = a.master + L.w_off;
+  const float* b = a.master + L.b_off;
+  const int kpf = kpad(L.cip);
+  const int nf = L.cop * kpf;
+  const int gcp = (L.co == 3) ? 8 : 32;  // channels of the gradient tensor
+  const int kpd = kpad(gcp);
+  const int nd = 32 * kpd;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < nf + nd + L.cop; i += gridDim.x * 256) {
+    if (i < nf) {
+      const int co = i / kpf, k = i - co * kpf;
+      const int tap = k / L.cip, ci = k - tap * L.cip;
+      float val = 0.0f;
+      if (co < L.co && ci < L.ci && tap < 9) val = w[((size_t)co * L.ci + ci) * 9 + tap];
+      a.wf[layer][i] = f2bf(val);
+    } else if (i < nf + nd) {
+      if (layer == 0) continue;  // the image gradient is never needed
+      const int j = i - nf;
+      const int ci = j / kpd, k = j - ci * kpd;
+      const int tapd = k / gcp, co = k - tapd * gcp;
+      float val = 0.0f;
+      if (co < L.co && ci < L.ci && tapd < 9) val = w[((size_t)co * L.ci + ci) * 9 + (8 - tapd)];
+      a.wd[layer][j] = f2bf(val);
+    } else {
+      const int co = i - nf - nd;
+      a.bias[layer][co] = co < L.co ? b[co] : 0.0f;
+    }
+  }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ state
+struct ils_net {
+  int max_B, max_H, max_W;
+  hipStream_t stream;
+  char* ws;
+  size_t ws_bytes;
+  int last_error;
+  long long step;
+  // device buffers (carved from the workspace)
+  float* master;
+  float* adam_m;
+  float* adam_v;
+  float* grad;
+  bf16* wf[6];
+  bf16* wd[6];
+  float* bias[6];
+  bf16* act[6];   // act[0] = x0 (8 ch), act[1..5] = a1..a5 (32 ch)
+  bf16* gbuf[2];  // gradient ping-pong (32 ch)
+  float* zbuf;    // v (B, 3, H, W) scratch
+  float* partial; // wgrad partials
+  double* lpart;  // loss partials
+  float* loss;
+};
+
+namespace {
+
+size_t net_layout(int B, int H, int W, ils_net* n) {
+  const size_t px = (size_t)B * H * W;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = al(off + bytes);
+    return o;
+  };
+  size_t o_master = take(kNet.nparams * 4), o_m = take(kNet.nparams * 4), o_v = take(kNet.nparams * 4),
+         o_g = take(kNet.nparams * 4);
+  size_t o_wf[6], o_wd[6], o_b[6];
+  for (int i = 0; i < 6; ++i) {
+    o_wf[i] = take((size_t)kNet.L[i].cop * kpad(kNet.L[i].cip) * 2);
+    o_wd[i] = take((size_t)32 * kpad(gchan(i)) * 2);
+    o_b[i] = take((size_t)kNet.L[i].cop * 4);
+  }
+  size_t o_act[6];
+  o_act[0] = take(px * 8 * 2);
+  for (int i = 1; i < 6; ++i) o_act[i] = take(px * 32 * 2);
+  size_t o_gb0 = take(px * 32 * 2), o_gb1 = take(px * 32 * 2);
+  size_t o_z = take(px * 3 * 4);
+  size_t o_part = take((size_t)kWgradBlocks * (32 * 32 * 9 + 32) * 4);
+  size_t o_lp = take(kLossBlocks * 8);
+  size_t o_loss = take(4);
+  if (n) {
+    char* b = n->ws;
+    n->master = (float*)(b + o_master);
+    n->adam_m = (float*)(b + o_m);
+    n->adam_v = (float*)(b + o_v);
+    n->grad = (float*)(b + o_g);
+    for (int i = 0; i < 6; ++i) {
+      n->wf[i] = (bf16*)(b + o_wf[i]);
+      n->wd[i] = (bf16*)(b + o_wd[i]);
+      n->bias[i] = (float*)(b + o_b[i]);
+      n->act[i] = (bf16*)(b + o_act[i]);
+    }
+    n->gbuf[0] = (bf16*)(b + o_gb0);
+    n->gbuf[1] = (bf16*)(b + o_gb1);
+    n->zbuf = (float*)(b + o_z);
+    n->partial = (float*)(b + o_part);
+    n->lpart = (double*)(b + o_lp);
+    n->loss = (float*)(b + o_loss);
+  }
+  return off;
+}
+
+int rec(ils_net* n, hipError_t e) {
+  if (e == hipSuccess) return ILS_OK;
+  if (n && n->last_error == ILS_OK) n->last_error = (int)e;
+  return ILS_ERR_HIP;
+}
+
+template <int CIP, int COP, int MODE>
+hipError_t conv(const ConvArgs& a, hipStream_t st) {
+  const int blocks = a.B * ((a.H + TH - 1) / TH) * ((a.W + TW - 1) / TW);
+  hipLaunchKernelGGL((k_conv<CIP, COP, MODE>), dim3(blocks), dim3(NTHREADS), 0, st, a);
+  return hipGetLastError();
+}
+
+// forward through the six layers; v written to `v` (planar fp32)
+hipError_t run_forward(ils_net* n, const float* f, const float* lam, const float* p, int B, int H, int W, float* v) {
+  hipStream_t st = n->stream;
+  const size_t px = (size_t)B * H * W;
+  int blocks = (int)((px + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_pack_input, dim3(blocks), dim3(256), 0, st, f, lam, p, n->act[0], B, H, W);
+  hipError_t e = hipGetLastError();
+  for (int i = 0; i < 6 && e == hipSuccess; ++i) {
+    ConvArgs a{};
+    a.in = n->act[i];
+    a.wfrag = n->wf[i];
+    a.bias = n->bias[i];
+    a.B = B;
+    a.H = H;
+    a.W = W;
+    if (i == 0) {
+      a.out = n->act[1];
+      e = conv<8, 32, CONV_RELU>(a, st);
+    } else if (i < 5) {
+      a.out = n->act[i + 1];
+      e = conv<32, 32, CONV_RELU>(a, st);
+    } else {
+      a.f = f;
+      a.v = v;
+      e = conv<32, 16, CONV_LAST>(a, st);
+    }
+  }
+  return e;
+}
+
+// gradients of the loss for the batch whose forward pass is in n->act / zbuf
+hipError_t run_backward(ils_net* n, const float* t, int B, int H, int W) {
+  hipStream_t st = n->stream;
+  const size_t px = (size_t)B * H * W;
+  hipLaunchKernelGGL(k_loss_grad, dim3(kLossBlocks), dim3(256), 0, st, n->zbuf, t, n->gbuf[0], n->lpart, B, H, W);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, st, n->lpart, kLossBlocks, 3.0 * (double)px, n->loss);
+  e = hipGetLastError();
+  int cur = 0;
+  for (int i = 5; i >= 0 && e == hipSuccess; --i) {
+    const Layer& L = kNet.L[i];
+    const bf16* g = n->gbuf[cur];
+    const bf16* x = n->act[i];
+    const int len = L.co * L.ci * 9 + L.co;
+    if (i == 5)
+      hipLaunchKernelGGL((k_wgrad<8, 32>), dim3(kWgradBlocks), dim3(256), 0, st, g, x, n->partial, L.co, L.ci, B, H, W);
+    else if (i == 0)
+      hipLaunchKernelGGL((k_wgrad<32, 8>), dim3(kWgradBlocks), dim3(256), 0, st, g, x, n->partial, L.co, L.ci, B, H, W);
+    else
+      hipLaunchKernelGGL((k_wgrad<32, 32>), dim3(kWgradBlocks), dim3(256), 0, st, g, x, n->partial, L.co, L.ci, B, H, W);
+    e = hipGetLastError();
+    if (e != hipSuccess) break;
+    hipLaunchKernelGGL(k_reduce_partials, dim3((len + 255) / 256), dim3(256), 0, st, n->partial, kWgradBlocks, len,
+                       n->grad + L.w_off);
+    e = hipGetLastError();
+    if (e != hipSuccess || i == 0) break;
+    ConvArgs a{};
+    a.in = g;
+    a.wfrag = n->wd[i];
+    a.out = n->gbuf[1 - cur];
+    a.mask = n->act[i];
+    a.B = B;
+    a.H = H;
+    a.W = W;
+    e = (i == 5) ? conv<8, 32, CONV_DGRAD>(a, st) : conv<32, 32, CONV_DGRAD>(a, st);
+    cur = 1 - cur;
+  }
+  return e;
+}
+
+hipError_t pack_weights(ils_net* n) {
+  PackArgs pa;
+  pa.master = n->master;
+  for (int i = 0; i < 6; ++i) {
+    pa.wf[i] = n->wf[i];
+    pa.wd[i] = n->wd[i];
+    pa.bias[i] = n->bias[i];
+  }
+  hipLaunchKernelGGL(k_pack_weights, dim3(16, 6), dim3(256), 0, n->stream, pa);
+  return hipGetLastError();
+}
+
+int check_batch(const ils_net* n, int B, int H, int W) {
+  if (B < 1 || H < 2 || W < 2 || B > n->max_B || H > n->max_H || W > n->max_W) return ILS_ERR_INVALID_ARG;
+  if (B > 512) return ILS_ERR_INVALID_ARG;
+  return ILS_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ C ABI
+extern "C" {
+
+int ils_net_param_count(void) { return (int)kNet.nparams; }
+
+size_t ils_net_workspace_bytes(int max_B, int max_H, int max_W) {
+  if (max_B < 1 || max_H < 2 || max_W < 2) return 0;
+  return net_layout(max_B, max_H, max_W, nullptr);
+}
+
+int ils_net_create(ils_net** out, int max_B, int max_H, int max_W, void* workspace, size_t ws_bytes,
+                   void* hip_stream) {
+  if (!out) return ILS_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (max_B < 1 || max_H < 2 || max_W < 2) return ILS_ERR_INVALID_ARG;
+  if (!workspace || ((uintptr_t)workspace & 255)) return ILS_ERR_WORKSPACE;
+  if (ws_bytes < ils_net_workspace_bytes(max_B, max_H, max_W)) return ILS_ERR_WORKSPACE;
+  ils_net* n = new (std::nothrow) ils_net();
+  if (!n) return ILS_ERR_HIP;
+  n->max_B = max_B;
+  n->max_H = max_H;
+  n->max_W = max_W;
+  n->stream = static_cast<hipStream_t>(hip_stream);
+  n->ws = static_cast<char*>(workspace);
+  n->ws_bytes = ws_bytes;
+  n->last_error = ILS_OK;
+  n->step = 0;
+  net_layout(max_B, max_H, max_W, n);
+  *out = n;
+  return ILS_OK;
+}
+
+int ils_net_set_stream(ils_net* n, void* hip_stream) {
+  if (!n) return ILS_ERR_INVALID_ARG;
+  n->stream = static_cast<hipStream_t>(hip_stream);
+  return ILS_OK;
+}
+
+int ils_net_set_state(ils_net* n, const float* params, const float* m, const float* v, long long step) {
+  if (!n || !params || step < 0) return ILS_ERR_INVALID_ARG;
+  const size_t bytes = kNet.nparams * 4;
+  hipError_t e = hipMemcpy(n->master, params, bytes, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = m ? hipMemcpy(n->adam_m, m, bytes, hipMemcpyHostToDevice) : hipMemset(n->adam_m, 0, bytes);
+  if (e == hipSuccess) e = v ? hipMemcpy(n->adam_v, v, bytes, hipMemcpyHostToDevice) : hipMemset(n->adam_v, 0, bytes);
+  if (e == hipSuccess) e = pack_weights(n);
+  if (e == hipSuccess) e = hipStreamSynchronize(n->stream);
+  n->step = step;
+  return rec(n, e);
+}
+
+int ils_net_get_state(ils_net* n, float* params, float* m, float* v, long long* step) {
+  if (!n) return ILS_ERR_INVALID_ARG;
+  const size_t bytes = kNet.nparams * 4;
+  hipError_t e = hipStreamSynchronize(n->stream);
+  if (e == hipSuccess && params) e = hipMemcpy(params, n->master, bytes, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && m) e = hipMemcpy(m, n->adam_m, bytes, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && v) e = hipMemcpy(v, n->adam_v, bytes, hipMemcpyDeviceToHost);
+  if (step) *step = n->step;
+  return rec(n, e);
+}
+
+int ils_net_forward(ils_net* n, const float* f, const float* lam, const float* p, int B, int H, int W, float* v) {
+  if (!n || !f || !lam || !p || !v) return ILS_ERR_INVALID_ARG;
+  int rc = check_batch(n, B, H, W);
+  if (rc != ILS_OK) return rc;
+  return rec(n, run_forward(n, f, lam, p, B, H, W, v));
+}
+
+int ils_net_gradients(ils_net* n, const float* f, const float* lam, const float* p, const float* target, int B, int H,
+                      int W, float* grad, float* loss) {
+  if (!n || !f || !lam || !p || !target || !grad || !loss) return ILS_ERR_INVALID_ARG;
+  int rc = check_batch(n, B, H, W);
+  if (rc != ILS_OK) return rc;
+  hipError_t e = run_forward(n, f, lam, p, B, H, W, n->zbuf);
+  if (e == hipSuccess) e = run_backward(n, target, B, H, W);
+  if (e == hipSuccess) e = hipMemcpyAsync(grad, n->grad, kNet.nparams * 4, hipMemcpyDeviceToDevice, n->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(loss, n->loss, 4, hipMemcpyDeviceToDevice, n->stream);
+  return rec(n, e);
+}
+
+int ils_net_train_step(ils_net* n, const float* f, const float* lam, const float* p, const float* target, int B,
+                       int H, int W, float lr, float* loss) {
+  if (!n || !f || !lam || !p || !target) return ILS_ERR_INVALID_ARG;
+  if (!(lr > 0.0f) || !std::isfinite(lr)) return ILS_ERR_INVALID_ARG;
+  int rc = check_batch(n, B, H, W);
+  if (rc != ILS_OK) return rc;
+  hipError_t e = run_forward(n, f, lam, p, B, H, W, n->zbuf);
+  if (e == hipSuccess) e = run_backward(n, target, B, H, W);
+  if (e == hipSuccess) {
+    n->step += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = (float)(1.0 - std::pow(0.9, (double)n->step));
+    const float c2 = (float)(1.0 - std::pow(0.999, (double)n->step));
+    const int np = (int)kNet.nparams;
+    hipLaunchKernelGGL(k_adam, dim3((np + 255) / 256), dim3(256), 0, n->stream, n->master, n->adam_m, n->adam_v,
+                       n->grad, np, lr, b1, b2, 1e-8f, c1, c2);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = pack_weights(n);
+  if (e == hipSuccess && loss) e = hipMemcpyAsync(loss, n->loss, 4, hipMemcpyDeviceToDevice, n->stream);
+  return rec(n, e);
+}
+
+int ils_net_last_error(ils_net* n) {
+  if (!n) return ILS_ERR_INVALID_ARG;
+  int r = n->last_error;
+  n->last_error = ILS_OK;
+  return r;
+}
+
+int ils_net_destroy(ils_net* n) {
+  delete n;
+  return ILS_OK;
+}
+
+// Residual-gated surrogate inference.  v = net(f); for every image
+// T(v) = one ILS iteration from u^0 = v with data term f; R = rms(T(v) - v);
+// images with R > tau are recomputed with plain ILS (N iterations) into out.
+int ils_surrogate_infer(ils_net* n, ils_plan* plan, const float* f, const float* lam_dev, const float* p_dev,
+                        const float* lam_host, const float* p_host, float eps, int N, int B, int H, int W,
+                        float tau, float* out, float* tv_scratch, float* residual_host, int* fallback_host) {
+  if (!n || !plan || !f || !lam_dev || !p_dev || !lam_host || !p_host || !out || !tv_scratch || !residual_host ||
+      !fallback_host)
+    return ILS_ERR_INVALID_ARG;
+  if (!std::isfinite(tau)) return ILS_ERR_NOT_CALIBRATED;
+  int rc = check_batch(n, B, H, W);
+  if (rc != ILS_OK) return rc;
+  for (int b = 0; b < B; ++b) {
+    rc = ils_check_args(H, W, 3, lam_host[b], p_host[b], eps, N);
+    if (rc != ILS_OK) return rc;
+  }
+  rc = ils_plan_set_stream(plan, n->stream);
+  if (rc != ILS_OK) return rc;
+  hipError_t e = run_forward(n, f, lam_dev, p_dev, B, H, W, out);
+  if (e != hipSuccess) return rec(n, e);
+  const size_t img = (size_t)3 * H * W;
+  std::vector<const float*> pa(B), pb(B);
+  std::vector<long long> cnt(B, (long long)img);
+  for (int b = 0; b < B; ++b) {
+    rc = ils_iterate_from(plan, f + b * img, out + b * img, H, W, 3, lam_host[b], p_host[b], eps, 1,
+                          tv_scratch + b * img);
+    if (rc != ILS_OK) return rc;
+    pa[b] = tv_scratch + b * img;
+    pb[b] = out + b * img;
+  }
+  // per-image residuals go to the loss-partial area of the network workspace
+  float* rms_dev = reinterpret_cast<float*>(n->lpart);
+  rc = ils_rms_diff(plan, pa.data(), pb.data(), cnt.data(), B, rms_dev);
+  if (rc != ILS_OK) return rc;
+  e = hipMemcpyAsync(residual_host, rms_dev, B * sizeof(float), hipMemcpyDeviceToHost, n->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(n->stream);
+  if (e != hipSuccess) return rec(n, e);
+  for (int b = 0; b < B; ++b) {
+    fallback_host[b] = !(residual_host[b] <= tau);  // NaN residual also falls back
+    if (fallback_host[b]) {
+      rc = ils_smooth(plan, f + b * img, H, W, 3, lam_host[b], p_host[b], eps, N, out + b * img);
+      if (rc != ILS_OK) return rc;
+    }
+  }
+  return ILS_OK;
+}
+
+}  // extern "C"

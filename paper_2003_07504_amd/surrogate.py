@@ -1,0 +1,221 @@
+"""Python binding of the learned surrogate (include/ils_net.h): argument
+marshalling only.  The forward and backward passes, the optimiser, the
+fixed-point residual and the fallback to plain ILS all run in libils.so.
+
+Network: six periodic 3x3 convolutions, 32 channels, ReLU after the first
+five; input = RGB image + constant lambda and p maps; output v = f + z6.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from ._lib import check, load
+
+__all__ = ["Net", "init_params", "layer_shapes", "param_count"]
+
+LAYERS = [(5, 32), (32, 32), (32, 32), (32, 32), (32, 32), (32, 3)]
+
+_SIGS = {
+    "ils_net_param_count": (ctypes.c_int, []),
+    "ils_net_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "ils_net_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                      ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "ils_net_set_stream": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "ils_net_set_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_longlong]),
+    "ils_net_get_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.POINTER(ctypes.c_longlong)]),
+    "ils_net_forward": (ctypes.c_int, [ctypes.c_void_p] * 4 + [ctypes.c_int] * 3 + [ctypes.c_void_p]),
+    "ils_net_gradients": (ctypes.c_int, [ctypes.c_void_p] * 5 + [ctypes.c_int] * 3 + [ctypes.c_void_p] * 2),
+    "ils_net_train_step": (ctypes.c_int, [ctypes.c_void_p] * 5 + [ctypes.c_int] * 3
+                           + [ctypes.c_float, ctypes.c_void_p]),
+    "ils_net_last_error": (ctypes.c_int, [ctypes.c_void_p]),
+    "ils_net_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "ils_surrogate_infer": (ctypes.c_int, [ctypes.c_void_p] * 7 + [ctypes.c_float, ctypes.c_int, ctypes.c_int,
+                                                                    ctypes.c_int, ctypes.c_int, ctypes.c_float]
+                            + [ctypes.c_void_p] * 4),
+}
+
+
+def _lib():
+    lib = load()
+    if not getattr(lib, "_net_sigs", False):
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        lib._net_sigs = True
+    return lib
+
+
+def layer_shapes():
+    """[(w shape, b shape)] in the flat parameter order."""
+    return [((co, ci, 3, 3), (co,)) for ci, co in LAYERS]
+
+
+def param_count() -> int:
+    return int(_lib().ils_net_param_count())
+
+
+def init_params(seed: int = 0) -> np.ndarray:
+    """He-normal weights, zero biases; the last layer scaled by 0.1 so the
+    untrained network starts near v = f."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for i, ((co, ci, _, _), (nb,)) in enumerate(layer_shapes()):
+        std = np.sqrt(2.0 / (9 * ci)) * (0.1 if i == len(LAYERS) - 1 else 1.0)
+        parts.append((rng.standard_normal((co, ci, 3, 3)) * std).ravel())
+        parts.append(np.zeros(nb))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def unflatten(flat: np.ndarray):
+    """Flat parameter vector -> [{"w": (co,ci,3,3), "b": (co,)}] (float64)."""
+    out, off = [], 0
+    for (ws, bs) in layer_shapes():
+        nw, nb = int(np.prod(ws)), int(np.prod(bs))
+        out.append({"w": np.asarray(flat[off:off + nw], dtype=np.float64).reshape(ws),
+                    "b": np.asarray(flat[off + nw:off + nw + nb], dtype=np.float64)})
+        off += nw + nb
+    return out
+
+
+def _vec(x, B, device, name):
+    if isinstance(x, torch.Tensor):
+        t = x.to(device=device, dtype=torch.float32).contiguous()
+    else:
+        t = torch.as_tensor(np.broadcast_to(np.asarray(x, dtype=np.float32), (B,)).copy(), device=device)
+    if t.numel() != B:
+        raise ValueError(f"{name} needs one value per image")
+    return t
+
+
+def _img(t: torch.Tensor, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.float32:
+        raise ValueError(f"{name} must be a float32 GPU tensor")
+    if t.dim() != 4 or t.shape[1] != 3 or not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous (B, 3, H, W)")
+    return t
+
+
+class Net:
+    def __init__(self, max_B: int, max_H: int, max_W: int, device=None, params: np.ndarray | None = None,
+                 seed: int = 0):
+        self._lib = _lib()
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        nbytes = int(self._lib.ils_net_workspace_bytes(max_B, max_H, max_W))
+        if nbytes == 0:
+            raise ValueError("invalid network limits")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p()
+        check(self._lib.ils_net_create(ctypes.byref(h), max_B, max_H, max_W,
+                                       ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
+                                       ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)),
+              "ils_net_create")
+        self._h = h
+        self.max_B, self.max_H, self.max_W = max_B, max_H, max_W
+        self.n = param_count()
+        self.set_state(init_params(seed) if params is None else params)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            torch.cuda.synchronize(self.device)
+            self._lib.ils_net_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _bind(self):
+        check(self._lib.ils_net_set_stream(
+            self._h, ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)), "ils_net_set_stream")
+
+    # -- state (checkpoint / resume) ----------------------------------------
+    def set_state(self, params, m=None, v=None, step: int = 0):
+        self._bind()
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.size != self.n:
+            raise ValueError(f"expected {self.n} parameters")
+        mm = None if m is None else np.ascontiguousarray(m, dtype=np.float32)
+        vv = None if v is None else np.ascontiguousarray(v, dtype=np.float32)
+        check(self._lib.ils_net_set_state(self._h, p.ctypes.data, None if mm is None else mm.ctypes.data,
+                                          None if vv is None else vv.ctypes.data, int(step)), "ils_net_set_state")
+
+    def get_state(self):
+        self._bind()
+        p = np.empty(self.n, dtype=np.float32)
+        m = np.empty(self.n, dtype=np.float32)
+        v = np.empty(self.n, dtype=np.float32)
+        st = ctypes.c_longlong()
+        check(self._lib.ils_net_get_state(self._h, p.ctypes.data, m.ctypes.data, v.ctypes.data, ctypes.byref(st)),
+              "ils_net_get_state")
+        return p, m, v, int(st.value)
+
+    def save(self, path: str, **extra):
+        p, m, v, st = self.get_state()
+        np.savez(path, params=p, m=m, v=v, step=np.int64(st), **extra)
+
+    def load(self, path: str) -> dict:
+        z = np.load(path, allow_pickle=False)
+        self.set_state(z["params"], z["m"], z["v"], int(z["step"]))
+        return {k: z[k] for k in z.files}
+
+    # -- compute -------------------------------------------------------------
+    def forward(self, f, lam, p, out=None):
+        f = _img(f, "f")
+        B, _, H, W = f.shape
+        lam_t, p_t = _vec(lam, B, self.device, "lam"), _vec(p, B, self.device, "p")
+        out = torch.empty_like(f) if out is None else _img(out, "out")
+        self._bind()
+        check(self._lib.ils_net_forward(self._h, f.data_ptr(), lam_t.data_ptr(), p_t.data_ptr(), B, H, W,
+                                        out.data_ptr()), "ils_net_forward")
+        return out
+
+    def gradients(self, f, lam, p, target):
+        f, target = _img(f, "f"), _img(target, "target")
+        B, _, H, W = f.shape
+        lam_t, p_t = _vec(lam, B, self.device, "lam"), _vec(p, B, self.device, "p")
+        grad = torch.empty(self.n, dtype=torch.float32, device=self.device)
+        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        self._bind()
+        check(self._lib.ils_net_gradients(self._h, f.data_ptr(), lam_t.data_ptr(), p_t.data_ptr(),
+                                          target.data_ptr(), B, H, W, grad.data_ptr(), loss.data_ptr()),
+              "ils_net_gradients")
+        return grad, loss
+
+    def train_step(self, f, lam, p, target, lr: float):
+        f, target = _img(f, "f"), _img(target, "target")
+        B, _, H, W = f.shape
+        lam_t, p_t = _vec(lam, B, self.device, "lam"), _vec(p, B, self.device, "p")
+        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        self._bind()
+        check(self._lib.ils_net_train_step(self._h, f.data_ptr(), lam_t.data_ptr(), p_t.data_ptr(),
+                                           target.data_ptr(), B, H, W, float(lr), loss.data_ptr()),
+              "ils_net_train_step")
+        return loss
+
+    def infer_gated(self, plan, f, lam, p, eps: float, N: int, tau: float, out=None):
+        """(out, residual[B], fallback[B]): surrogate output with plain-ILS
+        fallback where the fixed-point residual exceeds tau."""
+        f = _img(f, "f")
+        B, _, H, W = f.shape
+        lam_h = np.ascontiguousarray(np.broadcast_to(np.asarray(lam, dtype=np.float32), (B,)))
+        p_h = np.ascontiguousarray(np.broadcast_to(np.asarray(p, dtype=np.float32), (B,)))
+        lam_t = torch.as_tensor(lam_h, device=self.device)
+        p_t = torch.as_tensor(p_h, device=self.device)
+        out = torch.empty_like(f) if out is None else _img(out, "out")
+        scratch = torch.empty_like(f)
+        res = np.empty(B, dtype=np.float32)
+        fb = np.empty(B, dtype=np.int32)
+        self._bind()
+        check(self._lib.ils_surrogate_infer(self._h, plan._h, f.data_ptr(), lam_t.data_ptr(), p_t.data_ptr(),
+                                            lam_h.ctypes.data, p_h.ctypes.data, float(eps), int(N), B, H, W,
+                                            float(tau), out.data_ptr(), scratch.data_ptr(), res.ctypes.data,
+                                            fb.ctypes.data), "ils_surrogate_infer")
+        return out, res, fb.astype(bool)

@@ -10,10 +10,11 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "ils.h")
+NET_HEADER = os.path.join(ROOT, "include", "ils_net.h")
 
 
-def _declared():
-    text = open(HEADER).read()
+def _declared(path=HEADER):
+    text = open(path).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(ils_[a-z_0-9]+)\s*\(", text)))
 
@@ -38,6 +39,32 @@ def test_every_declared_symbol_is_exported(L):
         assert name in exported, name
         assert name in _lib.SIGNATURES, name
         getattr(L, name)
+
+
+def test_every_surrogate_symbol_is_exported(L):
+    from paper_2003_07504_amd import _lib, surrogate
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (ils_[a-z_0-9]+)$", out, flags=re.M))
+    names = _declared(NET_HEADER)
+    assert "ils_net_train_step" in names and "ils_surrogate_infer" in names
+    for name in names:
+        assert name in exported, name
+        assert name in surrogate._SIGS, name
+
+
+def test_surrogate_validation_without_gpu(L):
+    from paper_2003_07504_amd import surrogate
+    lib = surrogate._lib()
+    assert lib.ils_net_param_count() == 5 * 32 * 9 + 32 + 4 * (32 * 32 * 9 + 32) + 32 * 3 * 9 + 3
+    assert lib.ils_net_workspace_bytes(0, 8, 8) == 0
+    assert lib.ils_net_workspace_bytes(16, 256, 256) > 16 * 256 * 256 * 32 * 2 * 5
+    h = ctypes.c_void_p()
+    assert lib.ils_net_create(ctypes.byref(h), 1, 8, 8, None, 1 << 30, None) == -3
+    assert lib.ils_net_create(None, 1, 8, 8, None, 0, None) == -1
+    assert lib.ils_net_forward(None, None, None, None, 1, 8, 8, None) == -1
+    assert lib.ils_net_train_step(None, None, None, None, None, 1, 8, 8, 1e-3, None) == -1
+    assert lib.ils_net_destroy(None) == 0
+    assert len(surrogate.init_params(0)) == lib.ils_net_param_count()
 
 
 def test_smooth_signature_order_matches_header():
