@@ -83,6 +83,74 @@ def cpu_baseline(frames_np, H, W, C, lam, p, eps, N, seconds):
             "fps": round(done / el, 4)}
 
 
+def surrogate_gain(ring, H, W, weights, say):
+    """Learned surrogate with the residual gate against plain ILS at
+    N = 1..4 on the same frames (16 x 1080p RGB, per-frame lambda ~ U[0.5, 2],
+    p ~ U[0.5, 1]): time per frame and PSNR against plain ILS N = 4."""
+    import numpy as np
+    import torch
+
+    from paper_2003_07504_amd import ils, surrogate
+
+    B = len(ring)
+    rng = np.random.default_rng(3)
+    lam = rng.uniform(0.5, 2.0, B).astype(np.float32)
+    p = rng.uniform(0.5, 1.0, B).astype(np.float32)
+    f = torch.stack(ring).contiguous()
+    plan = ils.Plan(H, W, 3)
+    z = np.load(weights, allow_pickle=False)
+    tau = float(z["tau"])
+    net = surrogate.Net(B, H, W, params=z["params"])
+
+    def timed(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(reps):
+            out = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - a) / reps, out
+
+    res = {"frames": B, "tau": tau, "plain": {}}
+    refs = {}
+    for N in (1, 2, 3, 4):
+        outs = [torch.empty_like(ring[0]) for _ in range(B)]
+
+        def run_plain(N=N, outs=outs):
+            for b in range(B):
+                plan.smooth(f[b], float(lam[b]), float(p[b]), 1e-4, N, out=outs[b])
+            return outs
+        t, o = timed(run_plain)
+        refs[N] = torch.stack(o)
+        res["plain"][f"N{N}"] = {"ms_per_frame": round(t * 1e3 / B, 4)}
+
+    def psnr(a, b):
+        mse = torch.mean((a - b) ** 2, dim=(1, 2, 3))
+        return (10 * torch.log10(1.0 / mse)).cpu().numpy()
+
+    for N in (1, 2, 3):
+        res["plain"][f"N{N}"]["psnr_vs_N4_db"] = round(float(np.mean(psnr(refs[N], refs[4]))), 2)
+    say("surrogate: network forward and gated inference")
+    tnet, v = timed(lambda: net.forward(f, lam, p))
+    tg, (out, r, fb) = timed(lambda: net.infer_gated(plan, f, lam, p, 1e-4, 4, tau), reps=2)
+    ps_v = psnr(v, refs[4])
+    ps_g = psnr(out, refs[4])
+    res["surrogate"] = {
+        "network_ms_per_frame": round(tnet * 1e3 / B, 4),
+        "gated_ms_per_frame": round(tg * 1e3 / B, 4),
+        "psnr_vs_plain_N4_db_mean": round(float(np.mean(ps_v)), 2),
+        "psnr_vs_plain_N4_db_min": round(float(np.min(ps_v)), 2),
+        "gated_psnr_vs_plain_N4_db_mean": round(float(np.mean(ps_g)), 2),
+        "fallback_rate": round(float(np.mean(fb)), 4),
+        "residual_median": float(np.median(r)),
+        "weights_step": int(z["step"]),
+    }
+    res["gain_vs_plain_N4"] = round(res["plain"]["N4"]["ms_per_frame"] / res["surrogate"]["gated_ms_per_frame"], 3)
+    net.close()
+    plan.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,7 +159,8 @@ def main():
     ap.add_argument("--ring", type=int, default=16, help="distinct frames cycled through")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the hot-frame and batched figures")
+    ap.add_argument("--no-extras", action="store_true", help="skip the hot-frame, batched and surrogate figures")
+    ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2003_07504_amd", "weights", "surrogate.npz"))
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported: this build runs on one GPU only "
@@ -191,6 +260,8 @@ def main():
         bt = (time.perf_counter() - a) / (batches * nb)
         extras["batched_8_frames"] = {"ms_per_frame": round(bt * 1e3, 4), "fps": round(1 / bt, 1),
                                       "Mpixel_s": round(H * W / bt / 1e6, 1)}
+        if os.path.exists(args.weights):
+            extras["surrogate_gain"] = surrogate_gain(ring, H, W, args.weights, say)
 
     cpu = None
     if not args.no_cpu_baseline:

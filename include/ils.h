@@ -46,6 +46,9 @@ extern "C" {
 #define ILS_ERR_HIP -4              /* a HIP call failed (see ils_last_error)    */
 #define ILS_ERR_NOT_CALIBRATED -5   /* surrogate gate used without a threshold  */
 
+/* ils_plan_create flags. */
+#define ILS_PLAN_NO_GRAPH 1u /* enqueue batched calls kernel by kernel (no graph) */
+
 typedef struct ils_plan ils_plan;
 
 /* One frame of a batched call.  f / out: device pointers, C x H x W float32.
@@ -86,7 +89,10 @@ size_t ils_batch_workspace_bytes(const ils_frame* frames, int n);
  *                          tensor), at least ils_workspace_bytes(...) bytes,
  *                          256-byte aligned; it must outlive the plan.
  *   hip_stream           : hipStream_t to enqueue on (NULL = default stream).
- *   flags                : 0 (reserved).
+ *   flags                : 0, or ILS_PLAN_NO_GRAPH.  By default the pass
+ *                          sequence of a batched call is captured once as a
+ *                          HIP graph and replayed while the batch structure
+ *                          (sizes, channel counts, N) repeats.
  * The plan allocates only its own small device tables (FP64-computed
  * twiddles and Laplacian eigenvalues) and frees them in ils_plan_destroy.
  * Returns ILS_OK and sets *plan, or an error with *plan = NULL. */
@@ -112,7 +118,9 @@ int ils_iterate_from(ils_plan* plan, const float* f, const float* u0, int H, int
                      float lambda, float p, float eps, int N, float* out);
 
 /* Smooth n frames of possibly different sizes and parameters in one
- * enqueue (one launch per pass over all frames).  frames is a host array,
+ * enqueue: one launch per pass and size class over all its frames, the
+ * whole sequence replayed as one HIP graph (unless ILS_PLAN_NO_GRAPH or
+ * pass timing is active).  frames is a host array,
  * read during the call.  Each frame obeys the rules of ils_smooth.  The
  * workspace must hold ils_batch_workspace_bytes(frames, n). */
 int ils_smooth_batch(ils_plan* plan, const ils_frame* frames, int n);

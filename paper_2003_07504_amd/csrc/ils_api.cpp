@@ -86,6 +86,10 @@ struct ils_plan {
   hipEvent_t stage_ev[kStageSlots];
   bool stage_used[kStageSlots];
   int stage_next;
+  // graph of the last batched call (replayed while the batch structure repeats)
+  hipStream_t cap_stream;
+  hipGraphExec_t batch_exec;
+  std::vector<long long> batch_sig;
   // pass timing
   bool prof_on;
   std::vector<hipEvent_t> ev_pool;
@@ -143,6 +147,8 @@ static hipError_t timed(ils_plan* plan, int kind, F&& launch) {
 
 static void free_plan(ils_plan* plan) {
   for (hipEvent_t ev : plan->ev_pool) (void)hipEventDestroy(ev);
+  if (plan->batch_exec) (void)hipGraphExecDestroy(plan->batch_exec);
+  if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
   for (int i = 0; i < kStageSlots; ++i) {
     if (plan->stage_used[i]) (void)hipEventSynchronize(plan->stage_ev[i]);
     if (plan->stage_ev[i]) (void)hipEventDestroy(plan->stage_ev[i]);
@@ -280,7 +286,7 @@ int ils_plan_create(ils_plan** plan_out, int max_H, int max_W, int max_C, int ma
   if (!plan_out) return ILS_ERR_INVALID_ARG;
   *plan_out = nullptr;
   if (max_H < 2 || max_W < 2 || max_C < 1 || max_frames < 1) return ILS_ERR_INVALID_ARG;
-  if (flags != 0) return ILS_ERR_INVALID_ARG;
+  if (flags & ~(unsigned)ILS_PLAN_NO_GRAPH) return ILS_ERR_INVALID_ARG;
   if (!workspace || ((uintptr_t)workspace & 255)) return ILS_ERR_WORKSPACE;
   if (ws_bytes < ils_workspace_bytes(max_H, max_W, max_C, max_frames)) return ILS_ERR_WORKSPACE;
 
@@ -299,6 +305,8 @@ int ils_plan_create(ils_plan** plan_out, int max_H, int max_W, int max_C, int ma
   plan->stage_next = 0;
   plan->prof_on = false;
   plan->ev_used = 0;
+  plan->cap_stream = nullptr;
+  plan->batch_exec = nullptr;
   for (int i = 0; i < kStageSlots; ++i) {
     plan->stage[i] = nullptr;
     plan->stage_ev[i] = nullptr;
@@ -306,6 +314,11 @@ int ils_plan_create(ils_plan** plan_out, int max_H, int max_W, int max_C, int ma
   }
   if (hipGetDevice(&plan->device) != hipSuccess) {
     delete plan;
+    return ILS_ERR_HIP;
+  }
+  if (!(flags & ILS_PLAN_NO_GRAPH) &&
+      hipStreamCreateWithFlags(&plan->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    free_plan(plan);
     return ILS_ERR_HIP;
   }
   for (int i = 0; i < kStageSlots; ++i) {
@@ -569,27 +582,66 @@ int ils_smooth_batch(ils_plan* plan, const ils_frame* frames, int n) {
   int maxN = 0;
   for (const Launch& L : launches) maxN = L.N > maxN ? L.N : maxN;
   // Pass-major order: every class's pass k is enqueued before any pass k+1.
-  hipStream_t st = plan->stream;
+  auto enqueue = [&](hipStream_t st) -> hipError_t {
+    hipError_t r = hipSuccess;
+    for (const Launch& L : launches) {
+      r = timed(plan, 0, [&] { return L.orow->row(ilsk::ROW_FIRST, L.row, st); });
+      if (r != hipSuccess) return r;
+    }
+    for (int n = 0; n < maxN; ++n) {
+      for (const Launch& L : launches) {
+        if (n >= L.N) continue;
+        r = timed(plan, 3, [&] { return L.ocol->col(L.col, st); });
+        if (r != hipSuccess) return r;
+      }
+      for (const Launch& L : launches) {
+        if (n >= L.N) continue;
+        if (n + 1 < L.N)
+          r = timed(plan, 1, [&] { return L.orow->row(ilsk::ROW_MID, L.row, st); });
+        else
+          r = timed(plan, 2, [&] { return L.orow->row(ilsk::ROW_FINAL, L.fin, st); });
+        if (r != hipSuccess) return r;
+      }
+    }
+    return r;
+  };
+  if (plan->prof_on || !plan->cap_stream) return record(plan, enqueue(plan->stream));
+
+  // The whole 2N+1-pass sequence as one graph: the kernels read every frame
+  // parameter from the work lists in the workspace header, so a replay for a
+  // batch of the same structure needs no node updates.
+  std::vector<long long> sig;
+  sig.push_back((long long)hdr.size());
   for (const Launch& L : launches) {
-    e = timed(plan, 0, [&] { return L.orow->row(ilsk::ROW_FIRST, L.row, st); });
+    sig.push_back(L.orow->L);
+    sig.push_back(L.ocol->L);
+    sig.push_back(L.N);
+    sig.push_back(L.row.n);
+    sig.push_back(L.row.total);
+    sig.push_back(L.fin.total);
+    sig.push_back(L.col.total);
+  }
+  for (size_t o : offs) sig.push_back((long long)o);
+  if (!plan->batch_exec || sig != plan->batch_sig) {
+    if (plan->batch_exec) {
+      (void)hipGraphExecDestroy(plan->batch_exec);
+      plan->batch_exec = nullptr;
+    }
+    hipGraph_t g = nullptr;
+    e = hipStreamBeginCapture(plan->cap_stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return record(plan, e);
-  }
-  for (int n = 0; n < maxN; ++n) {
-    for (const Launch& L : launches) {
-      if (n >= L.N) continue;
-      e = timed(plan, 3, [&] { return L.ocol->col(L.col, st); });
-      if (e != hipSuccess) return record(plan, e);
+    hipError_t el = enqueue(plan->cap_stream);
+    e = hipStreamEndCapture(plan->cap_stream, &g);
+    if (el != hipSuccess) e = el;
+    if (e == hipSuccess) e = hipGraphInstantiate(&plan->batch_exec, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      plan->batch_exec = nullptr;
+      return record(plan, e);
     }
-    for (const Launch& L : launches) {
-      if (n >= L.N) continue;
-      if (n + 1 < L.N)
-        e = timed(plan, 1, [&] { return L.orow->row(ilsk::ROW_MID, L.row, st); });
-      else
-        e = timed(plan, 2, [&] { return L.orow->row(ilsk::ROW_FINAL, L.fin, st); });
-      if (e != hipSuccess) return record(plan, e);
-    }
+    plan->batch_sig = sig;
   }
-  return ILS_OK;
+  return record(plan, hipGraphLaunch(plan->batch_exec, plan->stream));
 }
 
 // ------------------------------------------------------------ debug passes

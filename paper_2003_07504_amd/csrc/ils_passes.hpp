@@ -225,30 +225,50 @@ __device__ __forceinline__ void row_body(const FrameDesc& d, int band, int ch, f
     __syncthreads();
   }
 
-  // ---- stencil + stage A (P-point forward) for output slots 1..Gv
+  // ---- stencil.  mu_y of row s (from rows s, s+1) is evaluated once by
+  // slot s and handed to slot s+1 through LDS; mu_x at x-1 is re-evaluated
+  // locally.  Slot 0 (the row above the band) only supplies mu_y.
+  const int t = lane;
   cf r[P];
-  if (out_slot && lane < Q) {
-    const int t = lane;
+  float2 myd[P];
+  const bool st_slot = slot <= Gv && lane < Q;  // slots 0..Gv evaluate mu_y
+  if (st_slot) {
     const float2* uc = reinterpret_cast<const float2*>(sl);
-    const float2* uu = reinterpret_cast<const float2*>(sl - SLOT_F);
     const float2* ud = reinterpret_cast<const float2*>(sl + SLOT_F);
     const float a_exp = d.a_exp, inv_eps = d.inv_eps, kappa = d.kappa;
     static_for<P>([&](auto n1c) {
       constexpr int n1 = decltype(n1c)::value;
       const int j = Q * n1 + t;
-      const int jm = (j == 0) ? M - 1 : j - 1;
-      const int jp = (j == M - 1) ? 0 : j + 1;
-      float2 c = uc[j], l = uc[jm], rr = uc[jp], up = uu[j], dn = ud[j];
-      float mxl = mu_ns(c.x - l.y, a_exp, inv_eps);
-      float mx0 = mu_ns(c.y - c.x, a_exp, inv_eps);
-      float mx1 = mu_ns(rr.x - c.y, a_exp, inv_eps);
-      float myu0 = mu_ns(c.x - up.x, a_exp, inv_eps);
-      float myu1 = mu_ns(c.y - up.y, a_exp, inv_eps);
-      float myd0 = mu_ns(dn.x - c.x, a_exp, inv_eps);
-      float myd1 = mu_ns(dn.y - c.y, a_exp, inv_eps);
-      float d0 = (mxl - mx0) + (myu0 - myd0);
-      float d1 = (mx0 - mx1) + (myu1 - myd1);
-      r[n1] = {fmaf(kappa, d0, fv[n1].x), fmaf(kappa, d1, fv[n1].y)};
+      const float2 c = uc[j], dn = ud[j];
+      myd[n1] = make_float2(mu_ns(dn.x - c.x, a_exp, inv_eps), mu_ns(dn.y - c.y, a_exp, inv_eps));
+      if (slot >= 1) {
+        const int jm = (j == 0) ? M - 1 : j - 1;
+        const int jp = (j == M - 1) ? 0 : j + 1;
+        const float2 l = uc[jm], rr = uc[jp];
+        const float mxl = mu_ns(c.x - l.y, a_exp, inv_eps);
+        const float mx0 = mu_ns(c.y - c.x, a_exp, inv_eps);
+        const float mx1 = mu_ns(rr.x - c.y, a_exp, inv_eps);
+        r[n1] = {fmaf(kappa, (mxl - mx0) - myd[n1].x, fv[n1].x), fmaf(kappa, (mx0 - mx1) - myd[n1].y, fv[n1].y)};
+      }
+    });
+  }
+  __syncthreads();  // every read of u done
+  if (st_slot && slot < Gv) {
+    float2* md = reinterpret_cast<float2*>(sl);
+    static_for<P>([&](auto n1c) {
+      constexpr int n1 = decltype(n1c)::value;
+      md[Q * n1 + t] = myd[n1];
+    });
+  }
+  __syncthreads();
+  // ---- add mu_y of the row above, then stage A (P-point forward)
+  if (out_slot && lane < Q) {
+    const float2* mu = reinterpret_cast<const float2*>(sl - SLOT_F);
+    const float kappa = d.kappa;
+    static_for<P>([&](auto n1c) {
+      constexpr int n1 = decltype(n1c)::value;
+      const float2 m = mu[Q * n1 + t];
+      r[n1] = {fmaf(kappa, m.x, r[n1].x), fmaf(kappa, m.y, r[n1].y)};
     });
     dft<P, -1>(r);
     static_for<P>([&](auto k1c) {

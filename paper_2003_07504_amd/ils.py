@@ -48,7 +48,7 @@ class Plan:
     max_frames frames may be resident in one batched call."""
 
     def __init__(self, max_H: int, max_W: int, max_C: int = 3, max_frames: int = 1, device=None,
-                 ws_bytes: int | None = None):
+                 ws_bytes: int | None = None, graph: bool = True):
         self._lib = load()
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         need = int(self._lib.ils_workspace_bytes(max_H, max_W, max_C, max_frames))
@@ -61,7 +61,7 @@ class Plan:
         with torch.cuda.device(self.device):
             check(self._lib.ils_plan_create(ctypes.byref(h), max_H, max_W, max_C, max_frames,
                                             ctypes.c_void_p(self.workspace.data_ptr()), ws_bytes,
-                                            ctypes.c_void_p(_stream_ptr(self.device)), 0),
+                                            ctypes.c_void_p(_stream_ptr(self.device)), 0 if graph else 1),
                   "ils_plan_create")
         self._h = h
 

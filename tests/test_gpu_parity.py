@@ -266,18 +266,52 @@ def test_batch_matches_single_frames(torch, ils):
     sizes = [(480, 640), (720, 1280), (256, 256), (90, 120)]
     specs = batch_mix(n=8, seed=2, sizes=sizes)
     frames = [(torch.from_numpy(s.image()).cuda(), s.lam, s.p, s.eps, s.N) for s in specs]
-    plan = ils.Plan(720, 1280, 3, max_frames=8)
-    outs = plan.smooth_batch(frames)
-    torch.cuda.synchronize()
-    assert plan.last_error() == 0
-    for (f, lam, p, eps, N), o, s in zip(frames, outs, specs):
+    singles = []
+    for f, lam, p, eps, N in frames:
         single = ils.Plan(f.shape[1], f.shape[2], f.shape[0])
-        u = single.smooth(f, lam, p, eps, N)
+        singles.append(single.smooth(f, lam, p, eps, N))
         torch.cuda.synchronize()
-        assert torch.equal(u, o), (s.H, s.W, s.C)
         single.close()
+    plan = ils.Plan(720, 1280, 3, max_frames=8)
+    # the batch runs as a captured graph: replay it several times with eager
+    # work and synchronisation in between, checking every replay
+    for rep in range(3):
+        outs = plan.smooth_batch(frames)
+        torch.cuda.synchronize()
+        assert plan.last_error() == 0
+        for u, o, s in zip(singles, outs, specs):
+            assert torch.equal(u, o), (rep, s.H, s.W, s.C)
+        junk = torch.randn(1 << 20, device="cuda").sum()  # eager work between replays
+        torch.cuda.synchronize()
+        del junk
     s = specs[0]
     ref = O.ils_channels(frames[0][0].cpu().numpy().astype(np.float64), s.lam, s.p, s.eps, s.N)
     ma, rl = _errs(outs[0].cpu().numpy(), ref)
     assert ma <= MAX_ABS and rl <= REL_L2
+    plan.close()
+    # the same batch without graph capture
+    plan = ils.Plan(720, 1280, 3, max_frames=8, graph=False)
+    outs = plan.smooth_batch(frames)
+    torch.cuda.synchronize()
+    for u, o in zip(singles, outs):
+        assert torch.equal(u, o)
+    plan.close()
+
+
+def test_batch_graph_changes_with_structure(torch, ils):
+    """A different batch structure re-captures; a repeated one replays with new
+    frame contents and parameters."""
+    _say("batch graph re-capture / replay with new data")
+    plan = ils.Plan(256, 256, 3, max_frames=4)
+    a = [torch.from_numpy(voronoi_image(256, 256, 1, 20, 0.05, seed=70 + i)).cuda() for i in range(4)]
+    for k, (n, lam) in enumerate([(2, 1.0), (3, 1.5), (3, 0.7), (2, 2.0)]):
+        frames = [(a[(i + k) % 4], lam, 0.8, 1e-4, 4) for i in range(n)]
+        outs = plan.smooth_batch(frames)
+        torch.cuda.synchronize()
+        for (f, lm, p, eps, N), o in zip(frames, outs):
+            single = ils.Plan(256, 256, 1)
+            u = single.smooth(f, lm, p, eps, N)
+            torch.cuda.synchronize()
+            assert torch.equal(u, o), (k, n)
+            single.close()
     plan.close()
