@@ -160,6 +160,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the hot-frame, batched and surrogate figures")
+    ap.add_argument("--copy-ref", action="store_true",
+                    help="also run one 512 MiB device-to-device copy (reference for HBM byte counters)")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2003_07504_amd", "weights", "surrogate.npz"))
     args = ap.parse_args()
     if args.gpus != 1:
@@ -231,6 +233,13 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
                 "avg_launch_us": dk["avg_us"], "alg_bytes_per_launch": dk["alg_bytes"]}
     step_alg = step_bytes(H, W, C, N)
+
+    if args.copy_ref:  # a copy of known size, to scale the profiler's byte counters
+        src = torch.empty(1 << 29, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     extras = {}
     if not args.no_extras:

@@ -37,6 +37,21 @@ __device__ __forceinline__ float mu_ns(float g, float a_exp, float inv_eps) {
   return fmaf(-g, pw, g);
 }
 
+// Synchronisation inside one row slot.  When a slot lies within one
+// wavefront (T divides 64) its LDS exchange needs no workgroup barrier: the
+// LDS operations of a wavefront are performed in program order, so it is
+// enough to keep the compiler from moving memory operations across this
+// point.  Otherwise fall back to a workgroup barrier.
+template <int T>
+__device__ __forceinline__ void slot_sync() {
+  if constexpr (64 % T == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  } else {
+    __syncthreads();
+  }
+}
+
 template <int P, int Q>
 struct RowGeom {
   static constexpr int M = P * Q;
@@ -47,13 +62,14 @@ struct RowGeom {
   static constexpr int NPOST = (M + 1 + T - 1) / T;  // post-process elements per lane
 };
 
-// Rows per row-pass workgroup: two workgroups per CU when the LDS allows it.
+// Rows per row-pass workgroup: two workgroups per CU (160 KB of LDS) when
+// that leaves bands of at least four rows, else one.
 template <int P, int Q>
 constexpr int row_band() {
   constexpr int slot = 4 * RowGeom<P, Q>::SLOT_F;
   constexpr int tab = 4 * RowGeom<P, Q>::TAB_F;
-  int g = (78000 - tab) / slot - 2;
-  if (g < 4) g = (155000 - tab) / slot - 2;
+  int g = (81920 - tab) / slot - 2;
+  if (g < 4) g = (163840 - tab) / slot - 2;
   if (g > 14) g = 14;
   if (g < 1) g = 1;
   return g;
@@ -64,9 +80,15 @@ struct ColGeom {
   static constexpr int H = P * Q;
   static constexpr int T = P > Q ? P : Q;
   static constexpr int TAB_F = 2 * H;  // twiddles exp(-2 pi i j / H)
+  // Widest tile whose exchange and table fit the 160 KB of LDS: 16 columns
+  // are whole 128-byte lines of the row-major spectrum (narrower tiles make
+  // neighbouring blocks fetch the same lines).
+  static constexpr int ex_bytes(int s) {
+    return 8 * P * ((s >= 16) ? Q * s : Q * s + ((s - (Q * s) % 16) + 16) % 16);
+  }
   static constexpr int pick_s() {
-    if (2 * P * Q * 16 * 4 + 4 * TAB_F <= 40000) return 16;
-    if (2 * P * (Q * 8 + 8) * 4 + 4 * TAB_F <= 80000) return 8;
+    if (ex_bytes(16) + 4 * TAB_F <= 163840 && 16 * (P > Q ? P : Q) <= 1024) return 16;
+    if (ex_bytes(8) + 4 * TAB_F <= 163840) return 8;
     return 4;
   }
   static constexpr int S = pick_s();
@@ -183,18 +205,23 @@ __device__ __forceinline__ void row_body(const FrameDesc& d, int band, int ch, f
 
   float2 fv[P];
   if constexpr (MODE == ROW_FIRST) {
-    const float* u0 = d.u0 + (size_t)ch * H * W;
-    for (int i = tid; i < (Gv + 2) * M; i += blockDim.x) {
-      int s = i / M, j = i - s * M;
-      int yy = y0 - 1 + s;
-      yy = yy < 0 ? yy + H : (yy >= H ? yy - H : yy);
-      float2 v = *reinterpret_cast<const float2*>(u0 + (size_t)yy * W + 2 * j);
-      reinterpret_cast<float2*>(smem + s * SLOT_F)[j] = v;
-    }
-    if (out_slot && lane < Q) {
+    if (in_slot && lane < Q) {  // u^0 row of this slot, all loads in flight together
+      const float2* urow = reinterpret_cast<const float2*>(d.u0 + (size_t)ch * H * W + (size_t)yrow * W);
+      float2 uv[P];
       static_for<P>([&](auto n1c) {
         constexpr int n1 = decltype(n1c)::value;
-        fv[n1] = frow[Q * n1 + lane];
+        uv[n1] = urow[Q * n1 + lane];
+      });
+      if (out_slot) {
+        static_for<P>([&](auto n1c) {
+          constexpr int n1 = decltype(n1c)::value;
+          fv[n1] = frow[Q * n1 + lane];
+        });
+      }
+      float2* u2 = reinterpret_cast<float2*>(sl);
+      static_for<P>([&](auto n1c) {
+        constexpr int n1 = decltype(n1c)::value;
+        u2[Q * n1 + lane] = uv[n1];
       });
     }
     __syncthreads();
@@ -211,10 +238,10 @@ __device__ __forceinline__ void row_body(const FrameDesc& d, int band, int ch, f
         fv[n1] = frow[Q * n1 + lane];
       });
     }
-    __syncthreads();
+    slot_sync<T>();
     cf z[P];
     if (in_slot && lane < Q) c2r_stage_b<P, Q>(slc, lane, z);
-    __syncthreads();
+    slot_sync<T>();
     if (in_slot && lane < Q) {
       float2* u2 = reinterpret_cast<float2*>(sl);
       static_for<P>([&](auto n1c) {
@@ -283,7 +310,7 @@ __device__ __forceinline__ void row_body(const FrameDesc& d, int band, int ch, f
       slc[k1 * QP + lane] = r[k1];
     });
   }
-  __syncthreads();
+  slot_sync<T>();
   cf zz[Q];
   if (out_slot && lane < P) {
     const int k1 = lane;
@@ -293,7 +320,7 @@ __device__ __forceinline__ void row_body(const FrameDesc& d, int band, int ch, f
     });
     dft<Q, -1>(zz);
   }
-  __syncthreads();
+  slot_sync<T>();
   if (out_slot && lane < P) {
     const int k1 = lane;
     static_for<Q>([&](auto k2c) {
@@ -301,7 +328,7 @@ __device__ __forceinline__ void row_body(const FrameDesc& d, int band, int ch, f
       slc[k1 + P * k2] = zz[k2];
     });
   }
-  __syncthreads();
+  slot_sync<T>();
   if (out_slot) r2c_post<P, Q>(slc, lane, w2lane, d.specA + (size_t)ch * H * ldS + (size_t)yout * ldS);
 }
 
@@ -332,7 +359,7 @@ __device__ __forceinline__ void row_final_body(const FrameDesc& d, int band, int
     const cf* X = d.specB + (size_t)ch * H * ldS + (size_t)yrow * ldS;
     c2r_stage_a<P, Q>(X, lane, cf{w2lane.x, -w2lane.y}, tws, slc);
   }
-  __syncthreads();
+  slot_sync<T>();
   if (in_slot && lane < Q) {
     cf z[P];
     c2r_stage_b<P, Q>(slc, lane, z);
