@@ -16,7 +16,6 @@ batched frames).
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -42,17 +41,6 @@ def step_bytes(H, W, C, N):
     return b["row_first"] + (N - 1) * b["row_mid"] + N * b["column"] + b["row_final"]
 
 
-def source_hash():
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2003_07504_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".hpp", ".cpp", ".def")):
-            with open(os.path.join(csrc, name), "rb") as fh:
-                h.update(name.encode())
-                h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
 def traffic_from_profiles(kernel, H, W, C):
     """HBM bytes per launch measured with rocprofv3 counters (committed under
     profiles/), or None when absent or taken on a different kernel source."""
@@ -62,9 +50,10 @@ def traffic_from_profiles(kernel, H, W, C):
     with open(path) as fh:
         t = json.load(fh)
     e = t.get(f"{kernel}@{H}x{W}x{C}")
-    if not e or e.get("source_hash") != source_hash():
+    from paper_2003_07504_amd.build import source_hash
+    if not e or e.get("source_hash") != source_hash() or "bytes_per_launch" not in e:
         return None
-    return e["bytes_per_launch"]
+    return e
 
 
 def cpu_baseline(frames_np, H, W, C, lam, p, eps, N, seconds):
@@ -149,6 +138,74 @@ def surrogate_gain(ring, H, W, weights, say):
     net.close()
     plan.close()
     return res
+
+
+def batch_mix_figures(say, reps=3):
+    """Uneven-size batch: 64 frames drawn from {640x480, 1280x720, 1920x1080,
+    3840x2160} x {grey, RGB} with per-frame lambda ~ U[0.5, 2], p ~ U[0.5, 1],
+    N = 4, smoothed by one ils_smooth_batch call (one graph replay).  One
+    distinct image per (size, channels) class is generated and shared by the
+    frames of that class (each frame keeps its own parameters and output)."""
+    import torch
+
+    from paper_2003_07504_amd import ils
+    from synth import batch_mix, voronoi_image
+
+    specs = batch_mix(n=64, seed=2)
+    imgs = {}
+    for s in specs:
+        if (s.H, s.W, s.C) not in imgs:
+            imgs[(s.H, s.W, s.C)] = torch.from_numpy(voronoi_image(s.H, s.W, s.C, s.K, s.sigma, s.seed)).cuda()
+    frames = [(imgs[(s.H, s.W, s.C)], s.lam, s.p, s.eps, s.N) for s in specs]
+    outs = [torch.empty_like(f[0]) for f in frames]
+    pxch = sum(s.H * s.W * s.C for s in specs)
+    px = sum(s.H * s.W for s in specs)
+    nbytes = sum(step_bytes(s.H, s.W, s.C, s.N) for s in specs)
+    from paper_2003_07504_amd._lib import IlsFrame, load
+    arr = (IlsFrame * len(frames))()
+    for i, (f, lam, p_, eps, N) in enumerate(frames):
+        C, H, W = f.shape
+        arr[i] = IlsFrame(f.data_ptr(), outs[i].data_ptr(), H, W, C, lam, p_, eps, N, 0)
+    need = int(load().ils_batch_workspace_bytes(arr, len(frames)))
+    plan = ils.Plan(2160, 3840, 3, max_frames=64, ws_bytes=need)
+    plan.smooth_batch(frames, outs=outs)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    for _ in range(reps):
+        plan.smooth_batch(frames, outs=outs)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - a) / reps
+    plan.close()
+    return {"frames": len(specs), "Mpx_ch": round(pxch / 1e6, 1), "ms_per_batch": round(t * 1e3, 3),
+            "fps": round(len(specs) / t, 1), "Mpixel_s": round(px / t / 1e6, 1),
+            "alg_GBs": round(nbytes / t / 1e9, 1), "distinct_images": len(imgs)}
+
+
+def stress_4k_figures(say, reps=2, distinct=8):
+    """32 x 3840x2160 RGB frames (2000 cells, sigma 0.08), lambda = 2,
+    p = 0.5, N = 10 in one batched call; `distinct` different frames cycled."""
+    import torch
+
+    from paper_2003_07504_amd import ils
+    from synth import voronoi_image
+
+    H, W, C, N = 2160, 3840, 3, 10
+    base = [torch.from_numpy(voronoi_image(H, W, C, 2000, 0.08, seed=5000 + i)).cuda() for i in range(distinct)]
+    frames = [(base[i % distinct], 2.0, 0.5, 1e-4, N) for i in range(32)]
+    outs = [torch.empty_like(base[0]) for _ in range(32)]
+    plan = ils.Plan(H, W, C, max_frames=32)  # 32 x 4K RGB spectra resident
+    plan.smooth_batch(frames, outs=outs)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    for _ in range(reps):
+        plan.smooth_batch(frames, outs=outs)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - a) / reps
+    plan.close()
+    nbytes = 32 * step_bytes(H, W, C, N)
+    return {"frames": 32, "N": N, "ms_per_batch": round(t * 1e3, 2), "fps": round(32 / t, 1),
+            "alg_GBs": round(nbytes / t / 1e9, 1), "alg_frac_of_8TBs": round(nbytes / t / 8e12, 4),
+            "distinct_frames": distinct}
 
 
 def main():
@@ -269,6 +326,10 @@ def main():
         bt = (time.perf_counter() - a) / (batches * nb)
         extras["batched_8_frames"] = {"ms_per_frame": round(bt * 1e3, 4), "fps": round(1 / bt, 1),
                                       "Mpixel_s": round(H * W / bt / 1e6, 1)}
+        say("uneven-size batch of 64 frames")
+        extras["batch_mix_64"] = batch_mix_figures(say)
+        say("4K RGB N=10 stress batch of 32 frames")
+        extras["stress_4k_n10_32"] = stress_4k_figures(say)
         if os.path.exists(args.weights):
             extras["surrogate_gain"] = surrogate_gain(ring, H, W, args.weights, say)
 

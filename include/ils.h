@@ -86,8 +86,10 @@ size_t ils_batch_workspace_bytes(const ils_frame* frames, int n);
 
 /* Create a plan.
  *   workspace / ws_bytes : caller-owned device memory (e.g. a torch uint8
- *                          tensor), at least ils_workspace_bytes(...) bytes,
- *                          256-byte aligned; it must outlive the plan.
+ *                          tensor), 256-byte aligned, at least
+ *                          ils_workspace_bytes(max_H, max_W, max_C, 1) bytes
+ *                          (batched calls need ils_batch_workspace_bytes of
+ *                          their frame list); it must outlive the plan.
  *   hip_stream           : hipStream_t to enqueue on (NULL = default stream).
  *   flags                : 0, or ILS_PLAN_NO_GRAPH.  By default the pass
  *                          sequence of a batched call is captured once as a

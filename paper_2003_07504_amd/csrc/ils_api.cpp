@@ -288,7 +288,8 @@ int ils_plan_create(ils_plan** plan_out, int max_H, int max_W, int max_C, int ma
   if (max_H < 2 || max_W < 2 || max_C < 1 || max_frames < 1) return ILS_ERR_INVALID_ARG;
   if (flags & ~(unsigned)ILS_PLAN_NO_GRAPH) return ILS_ERR_INVALID_ARG;
   if (!workspace || ((uintptr_t)workspace & 255)) return ILS_ERR_WORKSPACE;
-  if (ws_bytes < ils_workspace_bytes(max_H, max_W, max_C, max_frames)) return ILS_ERR_WORKSPACE;
+  // room for one frame of the largest size; batched calls check their exact need
+  if (ws_bytes < ils_workspace_bytes(max_H, max_W, max_C, 1)) return ILS_ERR_WORKSPACE;
 
   ils_plan* plan = new (std::nothrow) ils_plan();
   if (!plan) return ILS_ERR_HIP;

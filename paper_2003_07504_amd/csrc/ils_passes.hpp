@@ -107,13 +107,13 @@ __device__ __forceinline__ cf turn_half() {
 }
 
 // ---- C2R stage A' of one row (lane k1 < P): pre-process X[k], X[M-k] into
-// Z[k] = (X[k] + conj X[M-k]) + i (X[k] - conj X[M-k]) exp(i pi k / M),
-// Q-point inverse DFT over k2 (k = k1 + P k2), twiddle exp(2 pi i t k1 / M),
-// write the exchange row [k1][t].
+// Z[k] = (X[k] + conj X[M-k]) + i (X[k] - conj X[M-k]) exp(i pi k / M) and
+// take the Q-point inverse DFT over k2 (k = k1 + P k2); c2r_exchange then
+// applies the twiddle exp(2 pi i t k1 / M) and writes the exchange row
+// [k1][t].
 template <int P, int Q>
-__device__ __forceinline__ void c2r_stage_a(const cf* X, int k1, cf w1, const cf* tws, cf* slc) {
-  constexpr int M = P * Q, QP = Q | 1;
-  cf v[Q];
+__device__ __forceinline__ void c2r_stage_a(const cf* X, int k1, cf w1, cf (&v)[Q]) {
+  constexpr int M = P * Q;
   static_for<Q>([&](auto k2c) {
     constexpr int k2 = decltype(k2c)::value;
     const int k = k1 + P * k2;
@@ -131,6 +131,12 @@ __device__ __forceinline__ void c2r_stage_a(const cf* X, int k1, cf w1, const cf
     v[k2] = {e.x - o.y, e.y + o.x};  // e + i o
   });
   dft<Q, +1>(v);
+}
+
+// twiddle exp(2 pi i t k1 / M) from the LDS table, then the exchange row [k1][t]
+template <int P, int Q>
+__device__ __forceinline__ void c2r_exchange(const cf (&v)[Q], int k1, const cf* tws, cf* slc) {
+  constexpr int QP = Q | 1;
   static_for<Q>([&](auto tc) {
     constexpr int t = decltype(tc)::value;
     slc[k1 * QP + t] = (t == 0) ? v[t] : cmulc(v[t], tws[t * k1]);
@@ -226,11 +232,11 @@ __device__ __forceinline__ void row_body(const FrameDesc& d, int band, int ch, f
     }
     __syncthreads();
   } else {
-    __syncthreads();  // twiddle table ready
-    // ---- C2R of this slot's row
+    // ---- C2R of this slot's row (its loads overlap the table load)
+    cf v[Q];
     if (in_slot && lane < P) {
       const cf* X = d.specB + (size_t)ch * H * ldS + (size_t)yrow * ldS;
-      c2r_stage_a<P, Q>(X, lane, cf{w2lane.x, -w2lane.y}, tws, slc);
+      c2r_stage_a<P, Q>(X, lane, cf{w2lane.x, -w2lane.y}, v);
     }
     if (out_slot && lane < Q) {  // data term, in flight during the exchange
       static_for<P>([&](auto n1c) {
@@ -238,6 +244,8 @@ __device__ __forceinline__ void row_body(const FrameDesc& d, int band, int ch, f
         fv[n1] = frow[Q * n1 + lane];
       });
     }
+    __syncthreads();  // twiddle table ready
+    if (in_slot && lane < P) c2r_exchange<P, Q>(v, lane, tws, slc);
     slot_sync<T>();
     cf z[P];
     if (in_slot && lane < Q) c2r_stage_b<P, Q>(slc, lane, z);
@@ -354,11 +362,13 @@ __device__ __forceinline__ void row_final_body(const FrameDesc& d, int band, int
   const int yrow = in_slot ? y0 + slot : 0;
   const cf w2lane = d.tw2_row[lane];
   for (int i = tid; i < M; i += blockDim.x) tws[i] = d.tw_row[i];
-  __syncthreads();
+  cf v[Q];
   if (in_slot && lane < P) {
     const cf* X = d.specB + (size_t)ch * H * ldS + (size_t)yrow * ldS;
-    c2r_stage_a<P, Q>(X, lane, cf{w2lane.x, -w2lane.y}, tws, slc);
+    c2r_stage_a<P, Q>(X, lane, cf{w2lane.x, -w2lane.y}, v);
   }
+  __syncthreads();  // twiddle table ready
+  if (in_slot && lane < P) c2r_exchange<P, Q>(v, lane, tws, slc);
   slot_sync<T>();
   if (in_slot && lane < Q) {
     cf z[P];

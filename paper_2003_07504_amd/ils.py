@@ -54,7 +54,10 @@ class Plan:
         need = int(self._lib.ils_workspace_bytes(max_H, max_W, max_C, max_frames))
         if need == 0:
             raise ValueError("invalid plan limits")
-        ws_bytes = max(need, int(ws_bytes or 0))
+        # default: room for max_frames frames of the largest size; a caller that
+        # knows its batches may pass a smaller ws_bytes (at least one frame)
+        ws_bytes = need if ws_bytes is None else max(int(ws_bytes),
+                                                      int(self._lib.ils_workspace_bytes(max_H, max_W, max_C, 1)))
         self.workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=self.device)
         self.max_H, self.max_W, self.max_C, self.max_frames = max_H, max_W, max_C, max_frames
         h = ctypes.c_void_p()

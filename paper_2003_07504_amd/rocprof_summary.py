@@ -1,0 +1,111 @@
+"""Summarise rocprofv3 output (rocpd SQLite databases) of a bench.py run.
+
+    python -m paper_2003_07504_amd.rocprof_summary --trace KT.db --fetch F.db \
+        --write W.db [--sq S.db] --size 1080x1920x3 --command "<rocprofv3 ...>" \
+        --out profiles/ils_passes_1080p_rgb_n4.txt
+
+Writes a short text summary (per-kernel call counts and durations, HBM bytes
+per launch from FETCH_SIZE / WRITE_SIZE scaled by what the same counters
+read for a 512 MiB device copy, SQ counters) and records the bytes per
+launch in profiles/traffic.json under the current kernel-source hash, which
+bench.py uses for the roofline's `traffic` field.
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import json
+import os
+import re
+import sqlite3
+
+from .build import source_hash
+
+COPY_BYTES = 1 << 29
+KINDS = {"0": "row_first", "1": "row_mid", "2": "row_final"}
+
+
+def kind_of(name: str) -> str:
+    m = re.search(r"k_row<(\d+), (\d+), (\d)>", name)
+    if m:
+        return KINDS[m.group(3)]
+    if re.search(r"k_col<", name):
+        return "column"
+    if "copyBuffer" in name:
+        return "copy"
+    return re.sub(r"\(.*", "", name)[:48]
+
+
+def trace(db):
+    con = sqlite3.connect(db)
+    rows = con.execute("select name, count(*), avg(duration), min(duration), max(duration) "
+                       "from kernels group by name").fetchall()
+    return {kind_of(n): (n, c, a / 1e3, lo / 1e3, hi / 1e3) for n, c, a, lo, hi in rows}
+
+
+def counters(db):
+    con = sqlite3.connect(db)
+    rows = con.execute("select kernel_name, counter_name, avg(value) from counters_collection "
+                       "group by kernel_name, counter_name").fetchall()
+    d = collections.defaultdict(dict)
+    for kn, cn, v in rows:
+        d[kind_of(kn)][cn] = v
+    return d
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--trace", required=True)
+    ap.add_argument("--fetch", required=True)
+    ap.add_argument("--write", required=True)
+    ap.add_argument("--sq", default=None)
+    ap.add_argument("--size", required=True, help="HxWxC of the profiled workload")
+    ap.add_argument("--command", required=True, help="the rocprofv3 command line that produced the data")
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--traffic", default=os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                                                      "profiles", "traffic.json"))
+    a = ap.parse_args()
+    kt = trace(a.trace)
+    fe = counters(a.fetch)
+    wr = counters(a.write)
+    sq = counters(a.sq) if a.sq else {}
+    fscale = COPY_BYTES / (fe["copy"]["FETCH_SIZE"] * 1024.0)
+    wscale = COPY_BYTES / (wr["copy"]["WRITE_SIZE"] * 1024.0)
+    H, W, C = (int(v) for v in a.size.split("x"))
+    img = C * H * W * 4
+    spec = C * H * (W // 2 + 1) * 8
+    alg = {"row_first": img + spec, "row_mid": img + 2 * spec, "row_final": img + spec, "column": 2 * spec}
+    lines = [f"# rocprofv3 summary: ILS passes, {W}x{H}x{C} float32, N=4", "",
+             f"command: {a.command}", f"kernel source hash: {source_hash()}",
+             f"counter scale from a {COPY_BYTES >> 20} MiB copy: FETCH_SIZE x{fscale:.4f}, WRITE_SIZE x{wscale:.4f}",
+             "", f"{'pass':10s} {'calls':>5s} {'avg_us':>8s} {'min_us':>8s} {'max_us':>8s} "
+                 f"{'alg_MB':>8s} {'hbm_MB':>8s} {'rd_MB':>8s} {'wr_MB':>8s} {'alg_GB/s':>9s} {'hbm_GB/s':>9s}"]
+    traffic = {}
+    if os.path.exists(a.traffic):
+        with open(a.traffic) as fh:
+            traffic = json.load(fh)
+    for k in ("row_first", "row_mid", "column", "row_final"):
+        if k not in kt:
+            continue
+        name, calls, avg, lo, hi = kt[k]
+        rd = fe.get(k, {}).get("FETCH_SIZE", 0.0) * 1024 * fscale
+        wb = wr.get(k, {}).get("WRITE_SIZE", 0.0) * 1024 * wscale
+        lines.append(f"{k:10s} {calls:5d} {avg:8.3f} {lo:8.3f} {hi:8.3f} {alg[k] / 1e6:8.2f} {(rd + wb) / 1e6:8.2f} "
+                     f"{rd / 1e6:8.2f} {wb / 1e6:8.2f} {alg[k] / (avg * 1e3):9.1f} {(rd + wb) / (avg * 1e3):9.1f}")
+        traffic[f"{k}@{a.size}"] = {"bytes_per_launch": int(rd + wb), "read_bytes": int(rd), "write_bytes": int(wb),
+                                    "source_hash": source_hash(), "kernel": name}
+    if sq:
+        lines += ["", "SQ counters per launch (SQ_INSTS_* and SQ_WAVES per dispatch; cycles summed over SQs):"]
+        for k in ("row_first", "row_mid", "column", "row_final"):
+            if k in sq:
+                lines.append(f"  {k}: " + ", ".join(f"{cn}={v:.0f}" for cn, v in sorted(sq[k].items())))
+                traffic.setdefault(f"{k}@{a.size}", {})["sq"] = {cn: v for cn, v in sq[k].items()}
+    with open(a.out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    with open(a.traffic, "w") as fh:
+        json.dump(traffic, fh, indent=1)
+    print("\n".join(lines))
+
+
+if __name__ == "__main__":
+    main()

@@ -65,9 +65,12 @@ def residuals(plan, f_dev, u_dev, lam, p):
     tv = torch.empty_like(u_dev)
     for i in range(f_dev.shape[0]):
         plan.iterate_from(f_dev[i], u_dev[i], float(lam[i]), float(p[i]), 1e-4, 1, out=tv[i])
-    r = plan.rms_diff([tv[i] for i in range(tv.shape[0])], [u_dev[i] for i in range(u_dev.shape[0])])
+    out = []
+    for s in range(0, tv.shape[0], 512):  # at most 512 images per reduction call
+        e = min(s + 512, tv.shape[0])
+        out.append(plan.rms_diff([tv[i] for i in range(s, e)], [u_dev[i] for i in range(s, e)]))
     torch.cuda.synchronize()
-    return r.cpu().numpy()
+    return torch.cat(out).cpu().numpy()
 
 
 def psnr(a, b):

@@ -141,6 +141,9 @@ def test_plan_create_rejects_bad_arguments_before_hip(L):
     assert L.ils_plan_create(ctypes.byref(h), 8, 8, 1, 1, None, 1 << 30, None, 0) == -3
     assert L.ils_plan_create(ctypes.byref(h), 8, 8, 1, 1, ctypes.c_void_p(4096 + 8), 1 << 30, None, 0) == -3
     assert L.ils_plan_create(ctypes.byref(h), 8, 8, 1, 1, ctypes.c_void_p(4096), 16, None, 0) == -3
+    # the workspace must hold one frame of the largest size (batches are checked per call)
+    one = L.ils_workspace_bytes(1080, 1920, 3, 1)
+    assert L.ils_plan_create(ctypes.byref(h), 1080, 1920, 3, 8, ctypes.c_void_p(4096), one - 256, None, 0) == -3
     assert L.ils_plan_create(ctypes.byref(h), 8, 8, 1, 1, ctypes.c_void_p(4096), 1 << 30, None, 7) == -1
     assert h.value is None
 

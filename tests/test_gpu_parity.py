@@ -315,3 +315,35 @@ def test_batch_graph_changes_with_structure(torch, ils):
             assert torch.equal(u, o), (k, n)
             single.close()
     plan.close()
+
+
+def test_batch_mix_full_size(torch, ils):
+    """The 64-frame uneven-size batch at its real sizes (640x480 .. 3840x2160,
+    grey and RGB, per-frame lambda and p): every frame equals its single-frame
+    result bitwise and keeps the mean of each channel; two small frames are
+    compared with the oracle."""
+    _say("full uneven-size batch (64 frames)")
+    specs = batch_mix(n=64, seed=2)
+    frames = [(torch.from_numpy(s.image()).cuda(), s.lam, s.p, s.eps, s.N) for s in specs]
+    plan = ils.Plan(2160, 3840, 3, max_frames=64)
+    outs = plan.smooth_batch(frames)
+    torch.cuda.synchronize()
+    assert plan.last_error() == 0
+    single = ils.Plan(2160, 3840, 3)
+    for i, ((f, lam, p, eps, N), o, s) in enumerate(zip(frames, outs, specs)):
+        u = single.smooth(f, lam, p, eps, N)
+        torch.cuda.synchronize()
+        assert torch.equal(u, o), (i, s.H, s.W, s.C)
+        dm = (o.double().mean(dim=(1, 2)) - f.double().mean(dim=(1, 2))).abs().max().item()
+        assert dm < 2e-6, (i, dm)
+    checked = 0
+    for (f, lam, p, eps, N), o, s in zip(frames, outs, specs):
+        if s.H == 480 and checked < 2:
+            ref = O.ils_channels(f.cpu().numpy().astype(np.float64), lam, p, eps, N, workers=8)
+            ma, rl = _errs(o.cpu().numpy(), ref)
+            _say(f"  {s.W}x{s.H}x{s.C} lam={lam:.3f} p={p:.3f}: max_abs={ma:.3e} rel_l2={rl:.3e}")
+            assert ma <= MAX_ABS and rl <= REL_L2
+            checked += 1
+    assert checked == 2
+    single.close()
+    plan.close()
