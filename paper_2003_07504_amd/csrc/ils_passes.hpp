@@ -134,12 +134,19 @@ __device__ __forceinline__ void c2r_stage_a(const cf* X, int k1, cf w1, cf (&v)[
 }
 
 // twiddle exp(2 pi i t k1 / M) from the LDS table, then the exchange row [k1][t]
+// (All table reads are issued before the first exchange write: the table and
+// the exchange share one LDS array, so interleaving them would serialise.)
 template <int P, int Q>
 __device__ __forceinline__ void c2r_exchange(const cf (&v)[Q], int k1, const cf* tws, cf* slc) {
   constexpr int QP = Q | 1;
+  cf w[Q];
   static_for<Q>([&](auto tc) {
     constexpr int t = decltype(tc)::value;
-    slc[k1 * QP + t] = (t == 0) ? v[t] : cmulc(v[t], tws[t * k1]);
+    if constexpr (t > 0) w[t] = tws[t * k1];
+  });
+  static_for<Q>([&](auto tc) {
+    constexpr int t = decltype(tc)::value;
+    slc[k1 * QP + t] = (t == 0) ? v[t] : cmulc(v[t], w[t]);
   });
 }
 
@@ -161,19 +168,21 @@ template <int P, int Q>
 __device__ __forceinline__ void r2c_post(const cf* slc, int lane, cf wl, cf* Xo) {
   using Geo = RowGeom<P, Q>;
   constexpr int M = Geo::M, T = Geo::T;
-  static_for<Geo::NPOST>([&](auto ic) {
+  // every element but the last is in range (T (NPOST - 1) <= M), so only the
+  // last one is guarded and the rest stays one basic block
+  auto one = [&](auto ic) {
     constexpr int i = decltype(ic)::value;
     const int k = lane + T * i;
-    if (k <= M) {
-      cf A = slc[k == M ? 0 : k];
-      cf B = slc[k == 0 ? 0 : M - k];
-      B.y = -B.y;
-      const cf E = cadd(A, B), D = csub(A, B);
-      const cf w = (i == 0) ? wl : cmul(wl, turn_half<-(long long)T * i, M>());
-      const cf wD = cmul(D, w);
-      Xo[k] = {E.x + wD.y, E.y - wD.x};  // E - i wD
-    }
-  });
+    cf A = slc[k == M ? 0 : k];
+    cf B = slc[k == 0 ? 0 : M - k];
+    B.y = -B.y;
+    const cf E = cadd(A, B), D = csub(A, B);
+    const cf w = (i == 0) ? wl : cmul(wl, turn_half<-(long long)T * i, M>());
+    const cf wD = cmul(D, w);
+    Xo[k] = {E.x + wD.y, E.y - wD.x};  // E - i wD
+  };
+  static_for<Geo::NPOST - 1>(one);
+  if (lane + T * (Geo::NPOST - 1) <= M) one(std::integral_constant<int, Geo::NPOST - 1>{});
 }
 
 // --------------------------------------------------------------------------
@@ -238,14 +247,14 @@ __device__ __forceinline__ void row_body(const FrameDesc& d, int band, int ch, f
       const cf* X = d.specB + (size_t)ch * H * ldS + (size_t)yrow * ldS;
       c2r_stage_a<P, Q>(X, lane, cf{w2lane.x, -w2lane.y}, v);
     }
-    if (out_slot && lane < Q) {  // data term, in flight during the exchange
+    __syncthreads();  // twiddle table ready
+    if (in_slot && lane < P) c2r_exchange<P, Q>(v, lane, tws, slc);
+    if (out_slot && lane < Q) {  // data term, in flight during stage B'
       static_for<P>([&](auto n1c) {
         constexpr int n1 = decltype(n1c)::value;
         fv[n1] = frow[Q * n1 + lane];
       });
     }
-    __syncthreads();  // twiddle table ready
-    if (in_slot && lane < P) c2r_exchange<P, Q>(v, lane, tws, slc);
     slot_sync<T>();
     cf z[P];
     if (in_slot && lane < Q) c2r_stage_b<P, Q>(slc, lane, z);
@@ -271,21 +280,30 @@ __device__ __forceinline__ void row_body(const FrameDesc& d, int band, int ch, f
     const float2* uc = reinterpret_cast<const float2*>(sl);
     const float2* ud = reinterpret_cast<const float2*>(sl + SLOT_F);
     const float a_exp = d.a_exp, inv_eps = d.inv_eps, kappa = d.kappa;
-    static_for<P>([&](auto n1c) {
-      constexpr int n1 = decltype(n1c)::value;
-      const int j = Q * n1 + t;
-      const float2 c = uc[j], dn = ud[j];
-      myd[n1] = make_float2(mu_ns(dn.x - c.x, a_exp, inv_eps), mu_ns(dn.y - c.y, a_exp, inv_eps));
-      if (slot >= 1) {
+    if (slot >= 1) {
+      static_for<P>([&](auto n1c) {
+        constexpr int n1 = decltype(n1c)::value;
+        const int j = Q * n1 + t;
         const int jm = (j == 0) ? M - 1 : j - 1;
         const int jp = (j == M - 1) ? 0 : j + 1;
-        const float2 l = uc[jm], rr = uc[jp];
+        const float2 c = uc[j], dn = ud[j], l = uc[jm], rr = uc[jp];
+        myd[n1] = make_float2(mu_ns(dn.x - c.x, a_exp, inv_eps), mu_ns(dn.y - c.y, a_exp, inv_eps));
         const float mxl = mu_ns(c.x - l.y, a_exp, inv_eps);
         const float mx0 = mu_ns(c.y - c.x, a_exp, inv_eps);
         const float mx1 = mu_ns(rr.x - c.y, a_exp, inv_eps);
         r[n1] = {fmaf(kappa, (mxl - mx0) - myd[n1].x, fv[n1].x), fmaf(kappa, (mx0 - mx1) - myd[n1].y, fv[n1].y)};
-      }
-    });
+        // batches of five positions: their LDS reads issue together, while
+        // the registers of later positions are not claimed early
+        if constexpr ((n1 + 1) % 5 == 0) __builtin_amdgcn_sched_barrier(0);
+      });
+    } else {
+      static_for<P>([&](auto n1c) {
+        constexpr int n1 = decltype(n1c)::value;
+        const int j = Q * n1 + t;
+        const float2 c = uc[j], dn = ud[j];
+        myd[n1] = make_float2(mu_ns(dn.x - c.x, a_exp, inv_eps), mu_ns(dn.y - c.y, a_exp, inv_eps));
+      });
+    }
   }
   __syncthreads();  // every read of u done
   if (st_slot && slot < Gv) {
@@ -416,10 +434,15 @@ __device__ __forceinline__ void col_body(const FrameDesc& d, int tile, int ch, f
   for (int i = tid; i < H; i += blockDim.x) tws[i] = d.tw_col[i];
   __syncthreads();
   if (j < Q) {
+    cf w[P];
+    static_for<P>([&](auto k1c) {
+      constexpr int k1 = decltype(k1c)::value;
+      if constexpr (k1 > 0) w[k1] = tws[j * k1];
+    });
     dft<P, -1>(x);
     static_for<P>([&](auto k1c) {
       constexpr int k1 = decltype(k1c)::value;
-      ex[k1 * KS + j * S + s] = (k1 == 0) ? x[k1] : cmul(x[k1], tws[j * k1]);
+      ex[k1 * KS + j * S + s] = (k1 == 0) ? x[k1] : cmul(x[k1], w[k1]);
     });
   }
   __syncthreads();
