@@ -26,6 +26,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Mpixel/s and fps at 1080p RGB N=4 (FP32 ILS vs surrogate), HBM GB/s % peak"
 HBM_PEAK_GBS = 8000.0
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz: one non-packed VALU instruction per lane per clock
+VALU_PEAK_TLANE = round(256 * 4 * 16 * 2.4e9 / 1e12, 2)
 PAPER_1080P_RGB_MPX_S = 1920 * 1080 * 20 / 1e6  # 20 fps on a GTX 1080 (paper's GPU timing table)
 
 
@@ -41,8 +43,8 @@ def step_bytes(H, W, C, N):
     return b["row_first"] + (N - 1) * b["row_mid"] + N * b["column"] + b["row_final"]
 
 
-def traffic_from_profiles(kernel, H, W, C):
-    """HBM bytes per launch measured with rocprofv3 counters (committed under
+def profile_entry(kernel, H, W, C):
+    """Counter figures per launch measured with rocprofv3 (committed under
     profiles/), or None when absent or taken on a different kernel source."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
@@ -54,6 +56,35 @@ def traffic_from_profiles(kernel, H, W, C):
     if not e or e.get("source_hash") != source_hash() or "bytes_per_launch" not in e:
         return None
     return e
+
+
+def roofline_of(kernel, avg_us, alg_bytes, H, W, C):
+    """Roofline of the dominant kernel.  Two floors bound it: HBM bytes
+    (algorithmic bytes / 8 TB/s) and VALU issue (vector instructions the
+    kernel executes, counted by SQ_INSTS_VALU, x 64 lanes / the chip's
+    39.3 T lane-instructions per second with packed FP32 off).  `bound` is
+    the tighter of the two, i.e. the one with the larger fraction."""
+    hbm_ach = alg_bytes / (avg_us * 1e-6) / 1e9
+    hbm = {"achieved": round(hbm_ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(hbm_ach / HBM_PEAK_GBS, 4), "alg_bytes_per_launch": alg_bytes}
+    e = profile_entry(kernel, H, W, C)
+    traffic = e["bytes_per_launch"] if e else None
+    valu = (e or {}).get("sq", {}).get("SQ_INSTS_VALU")
+    out = {"bound": "hbm", **{k: hbm[k] for k in ("achieved", "peak", "unit", "frac")}, "traffic": traffic,
+           "kernel": kernel, "avg_launch_us": avg_us, "alg_bytes_per_launch": alg_bytes}
+    if valu:
+        lane = float(valu) * 64.0
+        ach = lane / (avg_us * 1e-6) / 1e12
+        alu = {"achieved": round(ach, 2), "peak": VALU_PEAK_TLANE, "unit": "T VALU lane-instr/s",
+               "frac": round(ach / VALU_PEAK_TLANE, 4), "valu_lane_instr_per_launch": int(lane)}
+        if alu["frac"] > hbm["frac"]:
+            out.update({"bound": "alu", **{k: alu[k] for k in ("achieved", "peak", "unit", "frac")},
+                        "valu_lane_instr_per_launch": alu["valu_lane_instr_per_launch"], "hbm": hbm})
+        else:
+            out["alu"] = alu
+    if e:
+        out["traffic_read_write"] = [e.get("read_bytes"), e.get("write_bytes")]
+    return out
 
 
 def cpu_baseline(frames_np, H, W, C, lam, p, eps, N, seconds):
@@ -284,11 +315,7 @@ def main():
                 for k, (t, n) in prof.items() if n > 0}
     dom = max(per_kind, key=lambda k: per_kind[k]["avg_us"] * per_kind[k]["launches"])
     dk = per_kind[dom]
-    achieved = dk["alg_GBs"]
-    traffic = traffic_from_profiles(dom, H, W, C)
-    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
-                "avg_launch_us": dk["avg_us"], "alg_bytes_per_launch": dk["alg_bytes"]}
+    roofline = roofline_of(dom, dk["avg_us"], dk["alg_bytes"], H, W, C)
     step_alg = step_bytes(H, W, C, N)
 
     if args.copy_ref:  # a copy of known size, to scale the profiler's byte counters

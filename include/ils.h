@@ -51,8 +51,15 @@ extern "C" {
 
 typedef struct ils_plan ils_plan;
 
+/* Penalty functions of the smoothness term. */
+#define ILS_PENALTY_CHARBONNIER 0 /* generalised Charbonnier phi_p, Eq. (5)    */
+#define ILS_PENALTY_WELSCH 1      /* Welsch phi_W, Eq. (18), c = 2 (Eq. (20))  */
+
 /* One frame of a batched call.  f / out: device pointers, C x H x W float32.
- * u0: device pointer of the first iterate, or NULL for u^0 = f (Alg. 1). */
+ * u0: device pointer of the first iterate, or NULL for u^0 = f (Alg. 1).
+ * penalty: ILS_PENALTY_CHARBONNIER (uses p and eps; gamma ignored) or
+ * ILS_PENALTY_WELSCH (uses gamma > 0; p and eps ignored).  A zeroed tail
+ * (penalty = 0) selects the Charbonnier penalty. */
 typedef struct ils_frame {
   const float* f;
   float* out;
@@ -60,6 +67,8 @@ typedef struct ils_frame {
   float lambda, p, eps;
   int N;
   const float* u0;
+  int penalty;
+  float gamma;
 } ils_frame;
 
 /* Human-readable name of a status code (static string). */
@@ -112,6 +121,15 @@ int ils_plan_set_stream(ils_plan* plan, void* hip_stream);
 int ils_smooth(ils_plan* plan, const float* f, int H, int W, int C, float lambda, float p,
                float eps, int N, float* out);
 
+/* Smooth one frame with the Welsch penalty (Sec. 5): Algorithm 1 with the
+ * pointwise step of Eq. (19), mu = c g - 2 g exp(-g^2 / (2 gamma^2)), and
+ * c = c0 = 2 (Eq. (20)); the linear solve of Eq. (9) is unchanged.
+ *   lambda >= 0 finite, gamma > 0 finite, N >= 0; other rules as ils_smooth.
+ * The paper's settings: N = 10 for clip-art artifact removal, N = 15 for
+ * texture smoothing, gamma = 5/255 .. 10/255. */
+int ils_smooth_welsch(ils_plan* plan, const float* f, int H, int W, int C, float lambda, float gamma,
+                      int N, float* out);
+
 /* As ils_smooth but starting from u^0 = u0 while the data term stays f
  * (N iterations of Eq. (7)-(9)).  With N = 1 this is the one-iteration map
  * T(u0) used to judge a candidate output by its fixed-point residual.
@@ -145,6 +163,29 @@ int ils_profile_end(ils_plan* plan, double* total_ms, int* count);
 
 /* Last asynchronous HIP error seen by the plan (ILS_OK if none); clears it. */
 int ils_last_error(ils_plan* plan);
+
+/* ---- tile shapes (the autotuner) ----
+ * Transform lengths of 480 and more are compiled with two row-band heights
+ * (rows per workgroup of the row passes) and two column-tile widths
+ * (spectrum columns per workgroup of the column pass).  Every shape runs the
+ * same arithmetic on every row and column, so the results are bitwise equal;
+ * only the speed differs.  The first smoothing call for a size H x W x C
+ * times the shapes on the plan's stream (a few launches on workspace data,
+ * one host synchronisation) and keeps the faster ones for the plan's life.
+ * A call made while the stream is being captured into a graph keeps the
+ * default shapes and leaves the size untuned.  Environment: ILS_TUNE=0
+ * keeps the defaults; ILS_TUNE_CACHE=<file> reads earlier choices at plan
+ * creation ("arch H W C row col" per line) and appends new ones.
+ *
+ * ils_shape_variants: number of row / column shapes for a supported size
+ *   (each 1 or 2).  ILS_ERR_UNSUPPORTED_SIZE otherwise.
+ * ils_plan_tune: tune the size now if it is not yet (synchronises the
+ *   plan's stream) and return the chosen shape indices (0 = default).
+ * ils_plan_set_shapes: fix the shapes for a size (indices below the counts
+ *   of ils_shape_variants, else ILS_ERR_INVALID_ARG); no GPU work. */
+int ils_shape_variants(int H, int W, int* n_row, int* n_col);
+int ils_plan_tune(ils_plan* plan, int H, int W, int C, int* row_shape, int* col_shape);
+int ils_plan_set_shapes(ils_plan* plan, int H, int W, int C, int row_shape, int col_shape);
 
 /* Destroy a plan (NULL is accepted).  Does not free the workspace. */
 int ils_plan_destroy(ils_plan* plan);

@@ -280,6 +280,10 @@ def ils_welsch(f, lam, gamma, N=10, workers=None):
     """Algorithm 1 with the Welsch penalty (Sec. 5): only the pointwise
     mu step and c change."""
     f = np.asarray(f, dtype=np.float64)
+    if f.ndim == 3:  # channels are independent problems (Sec. 3.4)
+        return np.stack([ils_welsch(ch, lam, gamma, N, workers) for ch in f])
+    if f.ndim != 2:
+        raise ValueError("ils_welsch expects (H, W) or (C, H, W)")
     c = welsch_c0()
     tf = transfer_functions(*f.shape)
     u = f.copy()

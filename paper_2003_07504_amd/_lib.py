@@ -26,7 +26,13 @@ class IlsFrame(ctypes.Structure):
         ("eps", ctypes.c_float),
         ("N", ctypes.c_int),
         ("u0", ctypes.c_void_p),
+        ("penalty", ctypes.c_int),
+        ("gamma", ctypes.c_float),
     ]
+
+
+PENALTY_CHARBONNIER = 0
+PENALTY_WELSCH = 1
 
 
 # name -> (restype, argtypes); exactly the functions include/ils.h declares.
@@ -45,6 +51,9 @@ SIGNATURES = {
     "ils_smooth": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                   ctypes.c_int, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                   ctypes.c_int, ctypes.c_void_p]),
+    "ils_smooth_welsch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                         ctypes.c_int, ctypes.c_float, ctypes.c_float, ctypes.c_int,
+                                         ctypes.c_void_p]),
     "ils_iterate_from": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                         ctypes.c_int, ctypes.c_int, ctypes.c_float, ctypes.c_float,
                                         ctypes.c_float, ctypes.c_int, ctypes.c_void_p]),
@@ -56,6 +65,12 @@ SIGNATURES = {
     "ils_profile_end": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_int)]),
     "ils_last_error": (ctypes.c_int, [ctypes.c_void_p]),
+    "ils_shape_variants": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                          ctypes.POINTER(ctypes.c_int)]),
+    "ils_plan_tune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                     ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
+    "ils_plan_set_shapes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                           ctypes.c_int, ctypes.c_int]),
     "ils_plan_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "ils_debug_rhs_spectrum": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                               ctypes.c_int, ctypes.c_int, ctypes.c_float, ctypes.c_float,

@@ -6,8 +6,12 @@
 
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <map>
+#include <string>
 #include <new>
 #include <vector>
 
@@ -17,7 +21,9 @@
 using ilsk::WorkList;
 using ilsk::cf;
 using ilsk::FrameDesc;
+using ilsk::ColVariant;
 using ilsk::LenOps;
+using ilsk::RowVariant;
 
 // ---------------------------------------------------------------- registry
 #define ILS_LEN(L, P, Q) const LenOps* ilsk_ops_##L();
@@ -90,6 +96,9 @@ struct ils_plan {
   hipStream_t cap_stream;
   hipGraphExec_t batch_exec;
   std::vector<long long> batch_sig;
+  // tile shapes chosen per image size (H, W, C) -> (row variant, column variant)
+  std::map<long long, std::pair<int, int>> tuned;
+  std::string arch;
   // pass timing
   bool prof_on;
   std::vector<hipEvent_t> ev_pool;
@@ -168,6 +177,19 @@ static int check_params(float lambda, float p, float eps, int N) {
   return ILS_OK;
 }
 
+static int check_params_welsch(float lambda, float gamma, int N) {
+  if (!finite_f(lambda) || lambda < 0.0f) return ILS_ERR_INVALID_ARG;
+  if (!finite_f(gamma) || !(gamma > 0.0f)) return ILS_ERR_INVALID_ARG;
+  if (N < 0) return ILS_ERR_INVALID_ARG;
+  return ILS_OK;
+}
+
+static int check_frame_params(const ils_frame& fr) {
+  if (fr.penalty == ILS_PENALTY_WELSCH) return check_params_welsch(fr.lambda, fr.gamma, fr.N);
+  if (fr.penalty != ILS_PENALTY_CHARBONNIER) return ILS_ERR_INVALID_ARG;
+  return check_params(fr.lambda, fr.p, fr.eps, fr.N);
+}
+
 static int check_size(const ils_plan* plan, int H, int W, int C) {
   if (H < 2 || W < 2 || C < 1) return ILS_ERR_INVALID_ARG;
   if (plan && (H > plan->max_H || W > plan->max_W || C > plan->max_C)) return ILS_ERR_INVALID_ARG;
@@ -198,6 +220,17 @@ static void fill_desc(const ils_plan* plan, FrameDesc& d, int H, int W, int C, f
   d.col_scale = (float)(1.0 / (2.0 * (double)H * (double)W));
 }
 
+// Welsch penalty (Sec. 5): c = c0 = 2 (Eq. (20)), so kappa = lambda; the
+// pointwise step takes w = -log2(e) / (2 gamma^2).
+static void fill_desc_welsch(const ils_plan* plan, FrameDesc& d, int H, int W, int C, float lambda,
+                             float gamma) {
+  fill_desc(plan, d, H, W, C, 1.0f, 1.0f, 1.0f);
+  const double g = (double)gamma;
+  d.kappa = lambda;
+  d.a_exp = (float)(-1.4426950408889634 / (2.0 * g * g));
+  d.inv_eps = 0.0f;
+}
+
 // Single-frame work lists for the three launch shapes of a frame.
 static WorkList one_frame(const FrameDesc& d, int items) {
   WorkList wl;
@@ -208,32 +241,132 @@ static WorkList one_frame(const FrameDesc& d, int items) {
   wl.total = items;
   return wl;
 }
-static int row_items(const LenOps* o, int mode, const FrameDesc& d) {
-  const int g = o->row_rows[mode];
+static int row_items(const RowVariant* v, int mode, const FrameDesc& d) {
+  const int g = v->rows[mode];
   return d.C * ((d.H + g - 1) / g);
 }
-static int col_items(const LenOps* o, const FrameDesc& d) {
-  const int s = o->col_cols;
+static int col_items(const ColVariant* v, const FrameDesc& d) {
+  const int s = v->cols;
   return d.C * ((d.W / 2 + 1 + s - 1) / s);
+}
+
+// ---------------------------------------------------------------- tuner
+// Lengths of 480 and more offer two row-band and two column-tile shapes.
+// The first call for an image size times each shape on the plan's stream
+// (HIP events, a few launches on workspace data, so it synchronises once)
+// and keeps the faster; the choice does not change any result bit, since
+// every row and column goes through the same arithmetic in either shape.
+// ILS_TUNE=0 keeps the default shapes; ILS_TUNE_CACHE names a text file of
+// earlier choices ("arch H W C row col" per line) that is read at plan
+// creation and appended to.
+struct Pick {
+  const RowVariant* rv;
+  const ColVariant* cv;
+};
+
+static long long size_key(int H, int W, int C) { return ((long long)H << 32) | ((long long)W << 8) | C; }
+
+static void load_tune_cache(ils_plan* plan) {
+  const char* path = std::getenv("ILS_TUNE_CACHE");
+  if (!path) return;
+  FILE* fh = std::fopen(path, "r");
+  if (!fh) return;
+  char arch[64];
+  int H, W, C, r, c;
+  while (std::fscanf(fh, "%63s %d %d %d %d %d", arch, &H, &W, &C, &r, &c) == 6)
+    if (plan->arch == arch && r >= 0 && r < 2 && c >= 0 && c < 2) plan->tuned[size_key(H, W, C)] = {r, c};
+  std::fclose(fh);
+}
+
+static float time_launches(ils_plan* plan, const std::function<hipError_t()>& launch) {
+  hipEvent_t a = nullptr, b = nullptr;
+  float best = 1e30f;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) best = -1.0f;
+  for (int rep = 0; rep < 4 && best >= 0.0f; ++rep) {
+    float ms = 0.0f;
+    if (launch() != hipSuccess || hipEventRecord(a, plan->stream) != hipSuccess || launch() != hipSuccess ||
+        launch() != hipSuccess || hipEventRecord(b, plan->stream) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+        hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+      best = -1.0f;
+      break;
+    }
+    best = ms < best ? ms : best;
+  }
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  return best;
+}
+
+static Pick choose(ils_plan* plan, const FrameDesc& d) {
+  const LenOps* orow = find_ops(d.W / 2);
+  const LenOps* ocol = find_ops(d.H);
+  Pick pk{&orow->row[0], &ocol->col[0]};
+  if (orow->nrow < 2 && ocol->ncol < 2) return pk;
+  const long long key = size_key(d.H, d.W, d.C);
+  auto it = plan->tuned.find(key);
+  if (it == plan->tuned.end()) {
+    std::pair<int, int> ch{0, 0};
+    const char* env = std::getenv("ILS_TUNE");
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    const bool capturing = hipStreamIsCapturing(plan->stream, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone;
+    // a stream under capture cannot be timed: such a call keeps the defaults
+    // and leaves the size untuned
+    if (capturing) return pk;
+    if (!(env && std::strcmp(env, "0") == 0) && !plan->prof_on) {
+      // time the shapes on the workspace (inputs and outputs point at the
+      // second half spectrum: any finite or non-finite data times the same)
+      FrameDesc t = d;
+      t.f = t.u0 = reinterpret_cast<const float*>(t.specB);
+      t.out = reinterpret_cast<float*>(t.specB);
+      float bestr = 1e30f, bestc = 1e30f;
+      for (int v = 0; v < orow->nrow; ++v) {
+        const WorkList wl = one_frame(t, row_items(&orow->row[v], ilsk::ROW_MID, t));
+        const float ms = time_launches(plan, [&] { return orow->row[v].launch(ilsk::ROW_MID, ilsk::PEN_CHARBONNIER, wl, plan->stream); });
+        if (ms >= 0.0f && ms < bestr) {
+          bestr = ms;
+          ch.first = v;
+        }
+      }
+      for (int v = 0; v < ocol->ncol; ++v) {
+        const WorkList wl = one_frame(t, col_items(&ocol->col[v], t));
+        const float ms = time_launches(plan, [&] { return ocol->col[v].launch(wl, plan->stream); });
+        if (ms >= 0.0f && ms < bestc) {
+          bestc = ms;
+          ch.second = v;
+        }
+      }
+      const char* path = std::getenv("ILS_TUNE_CACHE");
+      if (path) {
+        FILE* fh = std::fopen(path, "a");
+        if (fh) {
+          std::fprintf(fh, "%s %d %d %d %d %d\n", plan->arch.c_str(), d.H, d.W, d.C, ch.first, ch.second);
+          std::fclose(fh);
+        }
+      }
+    }
+    it = plan->tuned.emplace(key, ch).first;
+  }
+  pk.rv = &orow->row[it->second.first < orow->nrow ? it->second.first : 0];
+  pk.cv = &ocol->col[it->second.second < ocol->ncol ? it->second.second : 0];
+  return pk;
 }
 
 // Enqueue Algorithm 1 for one frame (N >= 1, lambda > 0): one block per
 // work item, 2N + 1 launches.
-static int run_frame(ils_plan* plan, const FrameDesc& d, int N) {
-  const LenOps* orow = find_ops(d.W / 2);
-  const LenOps* ocol = find_ops(d.H);
+static int run_frame(ils_plan* plan, const FrameDesc& d, int N, int pen = ilsk::PEN_CHARBONNIER) {
+  const Pick pk = choose(plan, d);
   hipStream_t st = plan->stream;
-  const WorkList wrow = one_frame(d, row_items(orow, ilsk::ROW_MID, d));
-  const WorkList wfin = one_frame(d, row_items(orow, ilsk::ROW_FINAL, d));
-  const WorkList wcol = one_frame(d, col_items(ocol, d));
-  hipError_t e = timed(plan, 0, [&] { return orow->row(ilsk::ROW_FIRST, wrow, st); });
+  const WorkList wrow = one_frame(d, row_items(pk.rv, ilsk::ROW_MID, d));
+  const WorkList wfin = one_frame(d, row_items(pk.rv, ilsk::ROW_FINAL, d));
+  const WorkList wcol = one_frame(d, col_items(pk.cv, d));
+  hipError_t e = timed(plan, 0, [&] { return pk.rv->launch(ilsk::ROW_FIRST, pen, wrow, st); });
   for (int n = 0; n < N && e == hipSuccess; ++n) {
-    e = timed(plan, 3, [&] { return ocol->col(wcol, st); });
+    e = timed(plan, 3, [&] { return pk.cv->launch(wcol, st); });
     if (e != hipSuccess) break;
     if (n + 1 < N)
-      e = timed(plan, 1, [&] { return orow->row(ilsk::ROW_MID, wrow, st); });
+      e = timed(plan, 1, [&] { return pk.rv->launch(ilsk::ROW_MID, pen, wrow, st); });
     else
-      e = timed(plan, 2, [&] { return orow->row(ilsk::ROW_FINAL, wfin, st); });
+      e = timed(plan, 2, [&] { return pk.rv->launch(ilsk::ROW_FINAL, pen, wfin, st); });
   }
   return record(plan, e);
 }
@@ -316,6 +449,13 @@ int ils_plan_create(ils_plan** plan_out, int max_H, int max_W, int max_C, int ma
   if (hipGetDevice(&plan->device) != hipSuccess) {
     delete plan;
     return ILS_ERR_HIP;
+  }
+  {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, plan->device) == hipSuccess) plan->arch = prop.gcnArchName;
+    const size_t colon = plan->arch.find(':');
+    if (colon != std::string::npos) plan->arch.resize(colon);
+    load_tune_cache(plan);
   }
   if (!(flags & ILS_PLAN_NO_GRAPH) &&
       hipStreamCreateWithFlags(&plan->cap_stream, hipStreamNonBlocking) != hipSuccess) {
@@ -428,6 +568,41 @@ int ils_last_error(ils_plan* plan) {
   return r;
 }
 
+int ils_shape_variants(int H, int W, int* n_row, int* n_col) {
+  if (!n_row || !n_col) return ILS_ERR_INVALID_ARG;
+  if (H < 2 || W < 2 || (W & 1) || !find_ops(H) || !find_ops(W / 2)) return ILS_ERR_UNSUPPORTED_SIZE;
+  *n_row = find_ops(W / 2)->nrow;
+  *n_col = find_ops(H)->ncol;
+  return ILS_OK;
+}
+
+int ils_plan_tune(ils_plan* plan, int H, int W, int C, int* row_shape, int* col_shape) {
+  if (!plan || !row_shape || !col_shape) return ILS_ERR_INVALID_ARG;
+  const int rc = check_size(plan, H, W, C);
+  if (rc != ILS_OK) return rc;
+  FrameDesc d;
+  fill_desc(plan, d, H, W, C, 1.0f, 1.0f, 1e-4f);
+  char* base = plan->ws + kBatchHeaderBytes;
+  d.specA = reinterpret_cast<cf*>(base);
+  d.specB = reinterpret_cast<cf*>(base + (size_t)C * H * d.ldS * sizeof(cf));
+  d.f = d.u0 = reinterpret_cast<const float*>(d.specB);
+  d.out = reinterpret_cast<float*>(d.specB);
+  const Pick pk = choose(plan, d);
+  *row_shape = (int)(pk.rv - find_ops(W / 2)->row);
+  *col_shape = (int)(pk.cv - find_ops(H)->col);
+  return ILS_OK;
+}
+
+int ils_plan_set_shapes(ils_plan* plan, int H, int W, int C, int row_shape, int col_shape) {
+  if (!plan) return ILS_ERR_INVALID_ARG;
+  const int rc = check_size(plan, H, W, C);
+  if (rc != ILS_OK) return rc;
+  if (row_shape < 0 || row_shape >= find_ops(W / 2)->nrow || col_shape < 0 || col_shape >= find_ops(H)->ncol)
+    return ILS_ERR_INVALID_ARG;
+  plan->tuned[size_key(H, W, C)] = {row_shape, col_shape};
+  return ILS_OK;
+}
+
 int ils_iterate_from(ils_plan* plan, const float* f, const float* u0, int H, int W, int C,
                      float lambda, float p, float eps, int N, float* out) {
   if (!plan || !f || !u0 || !out) return ILS_ERR_INVALID_ARG;
@@ -461,13 +636,38 @@ int ils_smooth(ils_plan* plan, const float* f, int H, int W, int C, float lambda
   return ils_iterate_from(plan, f, f, H, W, C, lambda, p, eps, N, out);
 }
 
+int ils_smooth_welsch(ils_plan* plan, const float* f, int H, int W, int C, float lambda, float gamma,
+                      int N, float* out) {
+  if (!plan || !f || !out) return ILS_ERR_INVALID_ARG;
+  int rc = check_params_welsch(lambda, gamma, N);
+  if (rc != ILS_OK) return rc;
+  rc = check_size(plan, H, W, C);
+  if (rc != ILS_OK) return rc;
+  const size_t need = frame_ws_bytes(H, W, C);
+  if (plan->ws_bytes < kBatchHeaderBytes + need) return ILS_ERR_WORKSPACE;
+  if (N == 0 || lambda == 0.0f) {
+    if (f == out) return ILS_OK;
+    return record(plan, hipMemcpyAsync(out, f, (size_t)C * H * W * sizeof(float), hipMemcpyDeviceToDevice,
+                                       plan->stream));
+  }
+  FrameDesc d;
+  fill_desc_welsch(plan, d, H, W, C, lambda, gamma);
+  d.f = f;
+  d.u0 = f;
+  d.out = out;
+  char* base = plan->ws + kBatchHeaderBytes;
+  d.specA = reinterpret_cast<cf*>(base);
+  d.specB = reinterpret_cast<cf*>(base + (size_t)C * H * d.ldS * sizeof(cf));
+  return run_frame(plan, d, N, ilsk::PEN_WELSCH);
+}
+
 int ils_smooth_batch(ils_plan* plan, const ils_frame* frames, int n) {
   if (!plan || !frames || n < 1) return ILS_ERR_INVALID_ARG;
   if (n > plan->max_frames || n > kMaxBatchFrames) return ILS_ERR_INVALID_ARG;
   for (int i = 0; i < n; ++i) {
     const ils_frame& fr = frames[i];
     if (!fr.f || !fr.out) return ILS_ERR_INVALID_ARG;
-    int rc = check_params(fr.lambda, fr.p, fr.eps, fr.N);
+    int rc = check_frame_params(fr);
     if (rc != ILS_OK) return rc;
     rc = check_size(plan, fr.H, fr.W, fr.C);
     if (rc != ILS_OK) return rc;
@@ -477,7 +677,7 @@ int ils_smooth_batch(ils_plan* plan, const ils_frame* frames, int n) {
 
   // Descriptors for every frame that needs iterations; trivial frames copy.
   std::vector<FrameDesc> descs;
-  std::vector<int> iters;
+  std::vector<int> iters, pens;
   char* base = plan->ws + kBatchHeaderBytes;
   size_t off = 0;
   for (int i = 0; i < n; ++i) {
@@ -494,7 +694,10 @@ int ils_smooth_batch(ils_plan* plan, const ils_frame* frames, int n) {
       continue;
     }
     FrameDesc d;
-    fill_desc(plan, d, fr.H, fr.W, fr.C, fr.lambda, fr.p, fr.eps);
+    if (fr.penalty == ILS_PENALTY_WELSCH)
+      fill_desc_welsch(plan, d, fr.H, fr.W, fr.C, fr.lambda, fr.gamma);
+    else
+      fill_desc(plan, d, fr.H, fr.W, fr.C, fr.lambda, fr.p, fr.eps);
     d.f = fr.f;
     d.u0 = u0;
     d.out = fr.out;
@@ -504,23 +707,24 @@ int ils_smooth_batch(ils_plan* plan, const ils_frame* frames, int n) {
     off += frame_ws_bytes(fr.H, fr.W, fr.C);
     descs.push_back(d);
     iters.push_back(fr.N);
+    pens.push_back(fr.penalty);
   }
   if (descs.empty()) return ILS_OK;
 
-  // Group frames into classes of equal (row length, column length, N):
-  // one launch per pass per class, each a persistent grid over the class's
+  // Group frames into classes of equal (row length, column length, N,
+  // penalty): one launch per pass per class, each a grid over the class's
   // (frame, channel, band) work list.
   struct Class {
-    int M, H, N;
+    int M, H, N, pen;
     std::vector<int> idx;
   };
   std::vector<Class> classes;
   for (size_t i = 0; i < descs.size(); ++i) {
-    int M = descs[i].W / 2, H = descs[i].H, N = iters[i];
+    int M = descs[i].W / 2, H = descs[i].H, N = iters[i], pen = pens[i];
     size_t c = 0;
     for (; c < classes.size(); ++c)
-      if (classes[c].M == M && classes[c].H == H && classes[c].N == N) break;
-    if (c == classes.size()) classes.push_back(Class{M, H, N, {}});
+      if (classes[c].M == M && classes[c].H == H && classes[c].N == N && classes[c].pen == pen) break;
+    if (c == classes.size()) classes.push_back(Class{M, H, N, pen, {}});
     classes[c].idx.push_back((int)i);
   }
 
@@ -534,25 +738,24 @@ int ils_smooth_batch(ils_plan* plan, const ils_frame* frames, int n) {
     return o;
   };
   struct Launch {
-    const LenOps* orow;
-    const LenOps* ocol;
-    int N;
+    Pick pk;
+    int N, pen;
     WorkList row, fin, col;
   };
   std::vector<Launch> launches;
   std::vector<size_t> offs;  // (desc, row starts, fin starts, col starts) per class
   for (const Class& cl : classes) {
     Launch L;
-    L.orow = find_ops(cl.M);
-    L.ocol = find_ops(cl.H);
+    L.pk = choose(plan, descs[cl.idx[0]]);
     L.N = cl.N;
+    L.pen = cl.pen;
     std::vector<FrameDesc> cd;
     std::vector<int> srow(1, 0), sfin(1, 0), scol(1, 0);
     for (int i : cl.idx) {
       const FrameDesc& d = descs[i];
       cd.push_back(d);
-      const int gr = L.orow->row_rows[ilsk::ROW_MID], gf = L.orow->row_rows[ilsk::ROW_FINAL];
-      const int sc = L.ocol->col_cols;
+      const int gr = L.pk.rv->rows[ilsk::ROW_MID], gf = L.pk.rv->rows[ilsk::ROW_FINAL];
+      const int sc = L.pk.cv->cols;
       srow.push_back(srow.back() + d.C * ((d.H + gr - 1) / gr));
       sfin.push_back(sfin.back() + d.C * ((d.H + gf - 1) / gf));
       scol.push_back(scol.back() + d.C * ((d.W / 2 + 1 + sc - 1) / sc));
@@ -586,21 +789,21 @@ int ils_smooth_batch(ils_plan* plan, const ils_frame* frames, int n) {
   auto enqueue = [&](hipStream_t st) -> hipError_t {
     hipError_t r = hipSuccess;
     for (const Launch& L : launches) {
-      r = timed(plan, 0, [&] { return L.orow->row(ilsk::ROW_FIRST, L.row, st); });
+      r = timed(plan, 0, [&] { return L.pk.rv->launch(ilsk::ROW_FIRST, L.pen, L.row, st); });
       if (r != hipSuccess) return r;
     }
     for (int n = 0; n < maxN; ++n) {
       for (const Launch& L : launches) {
         if (n >= L.N) continue;
-        r = timed(plan, 3, [&] { return L.ocol->col(L.col, st); });
+        r = timed(plan, 3, [&] { return L.pk.cv->launch(L.col, st); });
         if (r != hipSuccess) return r;
       }
       for (const Launch& L : launches) {
         if (n >= L.N) continue;
         if (n + 1 < L.N)
-          r = timed(plan, 1, [&] { return L.orow->row(ilsk::ROW_MID, L.row, st); });
+          r = timed(plan, 1, [&] { return L.pk.rv->launch(ilsk::ROW_MID, L.pen, L.row, st); });
         else
-          r = timed(plan, 2, [&] { return L.orow->row(ilsk::ROW_FINAL, L.fin, st); });
+          r = timed(plan, 2, [&] { return L.pk.rv->launch(ilsk::ROW_FINAL, L.pen, L.fin, st); });
         if (r != hipSuccess) return r;
       }
     }
@@ -614,9 +817,10 @@ int ils_smooth_batch(ils_plan* plan, const ils_frame* frames, int n) {
   std::vector<long long> sig;
   sig.push_back((long long)hdr.size());
   for (const Launch& L : launches) {
-    sig.push_back(L.orow->L);
-    sig.push_back(L.ocol->L);
+    sig.push_back((long long)(uintptr_t)L.pk.rv);
+    sig.push_back((long long)(uintptr_t)L.pk.cv);
     sig.push_back(L.N);
+    sig.push_back(L.pen);
     sig.push_back(L.row.n);
     sig.push_back(L.row.total);
     sig.push_back(L.fin.total);
@@ -661,8 +865,8 @@ int ils_debug_rhs_spectrum(ils_plan* plan, const float* f, const float* u0, int 
   char* base = plan->ws + kBatchHeaderBytes;
   d.specA = reinterpret_cast<cf*>(base);
   d.specB = reinterpret_cast<cf*>(base + (size_t)C * H * d.ldS * sizeof(cf));
-  const LenOps* o = find_ops(W / 2);
-  hipError_t e = o->row(ilsk::ROW_FIRST, one_frame(d, row_items(o, ilsk::ROW_FIRST, d)), plan->stream);
+  const RowVariant* v = &find_ops(W / 2)->row[0];
+  hipError_t e = v->launch(ilsk::ROW_FIRST, ilsk::PEN_CHARBONNIER, one_frame(d, row_items(v, ilsk::ROW_FIRST, d)), plan->stream);
   if (e == hipSuccess)
     e = hipMemcpy2DAsync(spec, (size_t)(W / 2 + 1) * sizeof(cf), d.specA, (size_t)d.ldS * sizeof(cf),
                          (size_t)(W / 2 + 1) * sizeof(cf), (size_t)C * H, hipMemcpyDeviceToDevice,
@@ -687,8 +891,8 @@ int ils_debug_column_solve(ils_plan* plan, const float* spec_in, int H, int W, i
   const size_t rowb = (size_t)(W / 2 + 1) * sizeof(cf);
   hipError_t e = hipMemcpy2DAsync(d.specA, (size_t)d.ldS * sizeof(cf), spec_in, rowb, rowb,
                                   (size_t)C * H, hipMemcpyDeviceToDevice, plan->stream);
-  const LenOps* oc = find_ops(H);
-  if (e == hipSuccess) e = oc->col(one_frame(d, col_items(oc, d)), plan->stream);
+  const ColVariant* cv = &find_ops(H)->col[0];
+  if (e == hipSuccess) e = cv->launch(one_frame(d, col_items(cv, d)), plan->stream);
   if (e == hipSuccess)
     e = hipMemcpy2DAsync(spec_out, rowb, d.specB, (size_t)d.ldS * sizeof(cf), rowb, (size_t)C * H,
                          hipMemcpyDeviceToDevice, plan->stream);
@@ -710,8 +914,8 @@ int ils_debug_row_inverse(ils_plan* plan, const float* spec, int H, int W, int C
   const size_t rowb = (size_t)(W / 2 + 1) * sizeof(cf);
   hipError_t e = hipMemcpy2DAsync(d.specB, (size_t)d.ldS * sizeof(cf), spec, rowb, rowb, (size_t)C * H,
                                   hipMemcpyDeviceToDevice, plan->stream);
-  const LenOps* o = find_ops(W / 2);
-  if (e == hipSuccess) e = o->row(ilsk::ROW_FINAL, one_frame(d, row_items(o, ilsk::ROW_FINAL, d)), plan->stream);
+  const RowVariant* v = &find_ops(W / 2)->row[0];
+  if (e == hipSuccess) e = v->launch(ilsk::ROW_FINAL, ilsk::PEN_CHARBONNIER, one_frame(d, row_items(v, ilsk::ROW_FINAL, d)), plan->stream);
   return record(plan, e);
 }
 

@@ -37,6 +37,24 @@ __device__ __forceinline__ float mu_ns(float g, float a_exp, float inv_eps) {
   return fmaf(-g, pw, g);
 }
 
+// Welsch penalty (Sec. 5, Eqs. (18)-(20)): with c = c0 = 2 the normalised
+// variable is mu / c = g (1 - exp(-g^2 / (2 gamma^2))); w = -log2(e) / (2 gamma^2).
+__device__ __forceinline__ float mu_ns_welsch(float g, float w) {
+  return fmaf(-g, __builtin_amdgcn_exp2f(w * (g * g)), g);
+}
+
+enum Penalty : int { PEN_CHARBONNIER = 0, PEN_WELSCH = 1 };
+
+// mu / c for the penalty of the kernel instance: (a, b) = (p/2 - 1, 1/eps)
+// for the generalised Charbonnier penalty, (w, unused) for Welsch.
+template <int PEN>
+__device__ __forceinline__ float mu_pen(float g, float a, float b) {
+  if constexpr (PEN == PEN_WELSCH)
+    return mu_ns_welsch(g, a);
+  else
+    return mu_ns(g, a, b);
+}
+
 // Synchronisation inside one row slot.  When a slot lies within one
 // wavefront (T divides 64) its LDS exchange needs no workgroup barrier: the
 // LDS operations of a wavefront are performed in program order, so it is
@@ -75,29 +93,44 @@ constexpr int row_band() {
   return g;
 }
 
+// Alternative offered to the tuner: one larger workgroup per CU (fewer halo
+// rows per output row, fewer and larger blocks).
 template <int P, int Q>
+constexpr int row_band_alt() {
+  constexpr int slot = 4 * RowGeom<P, Q>::SLOT_F;
+  constexpr int tab = 4 * RowGeom<P, Q>::TAB_F;
+  int g = (163840 - tab) / slot - 2;
+  if (g > 30) g = 30;
+  while ((g + 2) * RowGeom<P, Q>::T > 1024) --g;
+  if (g < 1) g = 1;
+  return g;
+}
+
+// Column tile of S spectrum columns.  The exchange row of one k1 is padded
+// so that successive k1 groups land on different LDS banks.
+template <int P, int Q, int S>
 struct ColGeom {
   static constexpr int H = P * Q;
   static constexpr int T = P > Q ? P : Q;
   static constexpr int TAB_F = 2 * H;  // twiddles exp(-2 pi i j / H)
-  // Widest tile whose exchange and table fit the 160 KB of LDS: 16 columns
-  // are whole 128-byte lines of the row-major spectrum (narrower tiles make
-  // neighbouring blocks fetch the same lines).
-  static constexpr int ex_bytes(int s) {
-    return 8 * P * ((s >= 16) ? Q * s : Q * s + ((s - (Q * s) % 16) + 16) % 16);
-  }
-  static constexpr int pick_s() {
-    if (ex_bytes(16) + 4 * TAB_F <= 163840 && 16 * (P > Q ? P : Q) <= 1024) return 16;
-    if (ex_bytes(8) + 4 * TAB_F <= 163840) return 8;
-    return 4;
-  }
-  static constexpr int S = pick_s();
-  // stride between k1 blocks of the exchange (in complex elements), padded so
-  // that successive k1 groups land on different LDS banks
   static constexpr int KS = (S >= 16) ? Q * S : Q * S + ((S - (Q * S) % 16) + 16) % 16;
   static constexpr int EX_F = 2 * P * KS;
   static constexpr int LDS_F = EX_F + TAB_F;
+  static constexpr bool fits = 4 * LDS_F <= 163840 && S * T <= 1024;
 };
+
+// Default column tile: the widest whose exchange and table fit the 160 KB of
+// LDS (16 columns are whole 128-byte lines of the row-major spectrum;
+// narrower tiles make neighbouring blocks fetch the same lines).  The
+// alternative offered to the tuner is the next narrower tile.
+template <int P, int Q>
+constexpr int col_tile() {
+  return ColGeom<P, Q, 16>::fits ? 16 : ColGeom<P, Q, 8>::fits ? 8 : 4;
+}
+template <int P, int Q>
+constexpr int col_tile_alt() {
+  return col_tile<P, Q>() > 4 ? col_tile<P, Q>() / 2 : 4;
+}
 
 // exp(+- i pi m / n) as a compile-time complex constant.
 template <long long m, long long n>
@@ -190,7 +223,7 @@ __device__ __forceinline__ void r2c_post(const cf* slc, int lane, cf wl, cf* Xo)
 // Slot s holds row y0 - 1 + s (periodic), s = 0 .. Gv + 1.
 // LDS: (G + 2) slots of SLOT_F floats, then the twiddle table.
 // --------------------------------------------------------------------------
-template <int P, int Q, int G, int MODE>
+template <int P, int Q, int G, int MODE, int PEN>
 __device__ __forceinline__ void row_body(const FrameDesc& d, int band, int ch, float* smem) {
   using Geo = RowGeom<P, Q>;
   constexpr int M = Geo::M, T = Geo::T, QP = Geo::QP, SLOT_F = Geo::SLOT_F;
@@ -287,10 +320,10 @@ __device__ __forceinline__ void row_body(const FrameDesc& d, int band, int ch, f
         const int jm = (j == 0) ? M - 1 : j - 1;
         const int jp = (j == M - 1) ? 0 : j + 1;
         const float2 c = uc[j], dn = ud[j], l = uc[jm], rr = uc[jp];
-        myd[n1] = make_float2(mu_ns(dn.x - c.x, a_exp, inv_eps), mu_ns(dn.y - c.y, a_exp, inv_eps));
-        const float mxl = mu_ns(c.x - l.y, a_exp, inv_eps);
-        const float mx0 = mu_ns(c.y - c.x, a_exp, inv_eps);
-        const float mx1 = mu_ns(rr.x - c.y, a_exp, inv_eps);
+        myd[n1] = make_float2(mu_pen<PEN>(dn.x - c.x, a_exp, inv_eps), mu_pen<PEN>(dn.y - c.y, a_exp, inv_eps));
+        const float mxl = mu_pen<PEN>(c.x - l.y, a_exp, inv_eps);
+        const float mx0 = mu_pen<PEN>(c.y - c.x, a_exp, inv_eps);
+        const float mx1 = mu_pen<PEN>(rr.x - c.y, a_exp, inv_eps);
         r[n1] = {fmaf(kappa, (mxl - mx0) - myd[n1].x, fv[n1].x), fmaf(kappa, (mx0 - mx1) - myd[n1].y, fv[n1].y)};
         // batches of five positions: their LDS reads issue together, while
         // the registers of later positions are not claimed early
@@ -301,7 +334,7 @@ __device__ __forceinline__ void row_body(const FrameDesc& d, int band, int ch, f
         constexpr int n1 = decltype(n1c)::value;
         const int j = Q * n1 + t;
         const float2 c = uc[j], dn = ud[j];
-        myd[n1] = make_float2(mu_ns(dn.x - c.x, a_exp, inv_eps), mu_ns(dn.y - c.y, a_exp, inv_eps));
+        myd[n1] = make_float2(mu_pen<PEN>(dn.x - c.x, a_exp, inv_eps), mu_pen<PEN>(dn.y - c.y, a_exp, inv_eps));
       });
     }
   }
@@ -406,10 +439,10 @@ __device__ __forceinline__ void row_final_body(const FrameDesc& d, int band, int
 // formed from the twiddle table (the squared term keeps full relative
 // precision at small l, where the other is negligible).
 // --------------------------------------------------------------------------
-template <int P, int Q>
+template <int P, int Q, int S_>
 __device__ __forceinline__ void col_body(const FrameDesc& d, int tile, int ch, float* smem) {
-  using Geo = ColGeom<P, Q>;
-  constexpr int H = Geo::H, S = Geo::S, KS = Geo::KS;
+  using Geo = ColGeom<P, Q, S_>;
+  constexpr int H = Geo::H, S = S_, KS = Geo::KS;
   const int ldS = d.ldS;
   const int Wh = d.W / 2 + 1;
   const int tid = threadIdx.x;

@@ -6,11 +6,11 @@ provides device memory (the workspace and the images) and the stream.
 from __future__ import annotations
 
 import ctypes
-from typing import Sequence
+from typing import NamedTuple, Sequence
 
 import torch
 
-from ._lib import IlsFrame, check, load
+from ._lib import PENALTY_CHARBONNIER, PENALTY_WELSCH, IlsFrame, check, load
 
 __all__ = ["Plan", "smooth", "size_supported", "workspace_bytes"]
 
@@ -100,6 +100,18 @@ class Plan:
         check(self._lib.ils_profile_end(self._h, tot, cnt), "ils_profile_end")
         return {k: (tot[i], cnt[i]) for i, k in enumerate(self.PASS_KINDS)}
 
+    # -- tile shapes -------------------------------------------------------
+    def tune(self, H: int, W: int, C: int) -> tuple[int, int]:
+        """Time the tile shapes for this size now (if not yet) and return the
+        chosen (row shape, column shape) indices."""
+        r, c = ctypes.c_int(), ctypes.c_int()
+        self._bind_stream()
+        check(self._lib.ils_plan_tune(self._h, H, W, C, ctypes.byref(r), ctypes.byref(c)), "ils_plan_tune")
+        return r.value, c.value
+
+    def set_shapes(self, H: int, W: int, C: int, row_shape: int, col_shape: int) -> None:
+        check(self._lib.ils_plan_set_shapes(self._h, H, W, C, int(row_shape), int(col_shape)), "ils_plan_set_shapes")
+
     # -- smoothing ---------------------------------------------------------
     def smooth(self, f: torch.Tensor, lam: float, p: float, eps: float = 1e-4, N: int = 4,
                out: torch.Tensor | None = None) -> torch.Tensor:
@@ -113,6 +125,21 @@ class Plan:
         self._bind_stream()
         check(self._lib.ils_smooth(self._h, ctypes.c_void_p(fc.data_ptr()), H, W, C, float(lam), float(p),
                                    float(eps), int(N), ctypes.c_void_p(oc.data_ptr())), "ils_smooth")
+        return out
+
+    def smooth_welsch(self, f: torch.Tensor, lam: float, gamma: float, N: int = 10,
+                      out: torch.Tensor | None = None) -> torch.Tensor:
+        """u^N of Algorithm 1 with the Welsch penalty (Sec. 5, c = 2)."""
+        fc = _as_chw(f, "f")
+        out = torch.empty_like(f) if out is None else out
+        oc = _as_chw(out, "out")
+        if oc.shape != fc.shape:
+            raise ValueError("out must have the shape of f")
+        C, H, W = fc.shape
+        self._bind_stream()
+        check(self._lib.ils_smooth_welsch(self._h, ctypes.c_void_p(fc.data_ptr()), H, W, C, float(lam),
+                                          float(gamma), int(N), ctypes.c_void_p(oc.data_ptr())),
+              "ils_smooth_welsch")
         return out
 
     def iterate_from(self, f: torch.Tensor, u0: torch.Tensor, lam: float, p: float, eps: float = 1e-4,
@@ -133,12 +160,19 @@ class Plan:
 
     def smooth_batch(self, frames: Sequence[tuple], outs: Sequence[torch.Tensor] | None = None,
                      u0s: Sequence[torch.Tensor | None] | None = None) -> list[torch.Tensor]:
-        """frames: sequence of (f, lam, p, eps, N); returns the outputs."""
+        """frames: sequence of (f, lam, p, eps, N) for the Charbonnier penalty
+        or Welsch(f, lam, gamma, N) frames; returns the outputs."""
         n = len(frames)
         arr = (IlsFrame * n)()
         keep = []
         res = []
-        for i, (f, lam, p, eps, N) in enumerate(frames):
+        for i, fr in enumerate(frames):
+            if isinstance(fr, Welsch):
+                f, lam, N = fr.f, fr.lam, fr.N
+                p, eps, pen, gamma = 1.0, 1.0, PENALTY_WELSCH, float(fr.gamma)
+            else:
+                f, lam, p, eps, N = fr
+                pen, gamma = PENALTY_CHARBONNIER, 0.0
             fc = _as_chw(f, f"frames[{i}].f")
             o = torch.empty_like(f) if outs is None else outs[i]
             oc = _as_chw(o, f"outs[{i}]")
@@ -146,7 +180,7 @@ class Plan:
             uc = None if u0 is None else _as_chw(u0, f"u0s[{i}]")
             C, H, W = fc.shape
             arr[i] = IlsFrame(fc.data_ptr(), oc.data_ptr(), H, W, C, float(lam), float(p), float(eps), int(N),
-                              0 if uc is None else uc.data_ptr())
+                              0 if uc is None else uc.data_ptr(), pen, gamma)
             keep.append((fc, oc, uc))
             res.append(o)
         need = int(self._lib.ils_batch_workspace_bytes(arr, n))
@@ -206,6 +240,21 @@ class Plan:
         check(self._lib.ils_debug_row_inverse(self._h, ctypes.c_void_p(spec.data_ptr()), H, W, C,
                                               ctypes.c_void_p(out.data_ptr())), "ils_debug_row_inverse")
         return out
+
+
+class Welsch(NamedTuple):
+    """A frame of a batched call smoothed with the Welsch penalty."""
+    f: torch.Tensor
+    lam: float
+    gamma: float
+    N: int = 10
+
+
+def shape_variants(H: int, W: int) -> tuple[int, int]:
+    """Number of compiled (row, column) tile shapes for a supported size."""
+    r, c = ctypes.c_int(), ctypes.c_int()
+    check(load().ils_shape_variants(H, W, ctypes.byref(r), ctypes.byref(c)), "ils_shape_variants")
+    return r.value, c.value
 
 
 _plans: dict = {}

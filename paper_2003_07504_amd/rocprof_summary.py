@@ -26,9 +26,9 @@ KINDS = {"0": "row_first", "1": "row_mid", "2": "row_final"}
 
 
 def kind_of(name: str) -> str:
-    m = re.search(r"k_row<(\d+), (\d+), (\d)>", name)
+    m = re.search(r"k_row<(\d+), (\d+), (\d+), (\d), (\d)>", name)
     if m:
-        return KINDS[m.group(3)]
+        return KINDS[m.group(4)] + ("_welsch" if m.group(5) == "1" else "")
     if re.search(r"k_col<", name):
         return "column"
     if "copyBuffer" in name:

@@ -159,3 +159,36 @@ def test_workspace_bytes(L):
     arr[0] = IlsFrame(None, None, 480, 640, 1, 1.0, 0.8, 1e-4, 4, None)
     arr[1] = IlsFrame(None, None, 1080, 1920, 3, 1.0, 0.8, 1e-4, 4, None)
     assert L.ils_batch_workspace_bytes(arr, 2) == (1 << 20) + 2 * 480 * 336 * 8 + 2 * 3 * 1080 * 976 * 8
+
+
+@pytest.mark.parametrize("H,W,nr,nc", [(1080, 1920, 2, 2), (2160, 3840, 1, 2), (256, 256, 1, 1), (480, 640, 1, 2)])
+def test_shape_variants(L, H, W, nr, nc):
+    from paper_2003_07504_amd import ils
+    assert ils.shape_variants(H, W) == (nr, nc)
+
+
+def test_shape_entry_points_reject_bad_arguments(L):
+    r, c = ctypes.c_int(), ctypes.c_int()
+    assert L.ils_shape_variants(1080, 1921, ctypes.byref(r), ctypes.byref(c)) == -2
+    assert L.ils_shape_variants(1080, 1920, None, None) == -1
+    assert L.ils_plan_tune(None, 1080, 1920, 3, ctypes.byref(r), ctypes.byref(c)) == -1
+    assert L.ils_plan_set_shapes(None, 1080, 1920, 3, 0, 0) == -1
+
+
+def test_frame_struct_layout_matches_c(tmp_path):
+    """ctypes mirror of ils_frame has the C compiler's size and offsets."""
+    from paper_2003_07504_amd._lib import IlsFrame
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "ils.h"\n'
+                   'int main(void) { printf("%zu %zu %zu %zu %zu\\n", sizeof(ils_frame), '
+                   'offsetof(ils_frame, N), offsetof(ils_frame, u0), offsetof(ils_frame, penalty), '
+                   'offsetof(ils_frame, gamma)); return 0; }\n')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    assert got == [ctypes.sizeof(IlsFrame), IlsFrame.N.offset, IlsFrame.u0.offset, IlsFrame.penalty.offset,
+                   IlsFrame.gamma.offset]
+
+
+def test_welsch_entry_point_rejects_null_plan(L):
+    assert L.ils_smooth_welsch(None, None, 8, 8, 1, 20.0, 0.04, 10, None) == -1

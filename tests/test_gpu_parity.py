@@ -347,3 +347,41 @@ def test_batch_mix_full_size(torch, ils):
     assert checked == 2
     single.close()
     plan.close()
+
+
+# ------------------------------------------------------------ tile shapes (autotuner)
+@pytest.mark.parametrize("H,W,C", [(1080, 1920, 3), (720, 1280, 1), (2160, 3840, 1)])
+def test_tile_shapes_are_bitwise_equal(torch, ils, H, W, C):
+    """Every compiled row-band / column-tile shape gives the same bits, in
+    single and batched calls, and the tuner picks one of them."""
+    nr, nc = ils.shape_variants(H, W)
+    _say(f"tile shapes H={H} W={W} C={C}: {nr} row x {nc} column")
+    f = [voronoi_image(H, W, C, 400, 0.05, seed=77 + i) for i in range(2)]
+    ft = [torch.from_numpy(x).cuda() for x in f]
+    plan = ils.Plan(H, W, C, max_frames=2)
+    ref = None
+    for r in range(nr):
+        for c in range(nc):
+            plan.set_shapes(H, W, C, r, c)
+            u = plan.smooth(ft[0], 1.0, 0.8, 1e-4, 4)
+            ub = plan.smooth_batch([(ft[0], 1.0, 0.8, 1e-4, 4), (ft[1], 1.7, 0.6, 1e-4, 3)])
+            torch.cuda.synchronize()
+            assert plan.last_error() == 0
+            got = (u.cpu().numpy(), ub[0].cpu().numpy(), ub[1].cpu().numpy())
+            assert np.array_equal(got[0], got[1]), (r, c)
+            if ref is None:
+                ref = got
+            else:
+                for a, b in zip(got, ref):
+                    assert np.array_equal(a, b), (r, c)
+    plan.close()
+    fresh = ils.Plan(H, W, C)
+    rt, ct = fresh.tune(H, W, C)
+    assert 0 <= rt < nr and 0 <= ct < nc
+    assert fresh.tune(H, W, C) == (rt, ct)
+    u = fresh.smooth(ft[0], 1.0, 0.8, 1e-4, 4)
+    torch.cuda.synchronize()
+    assert np.array_equal(u.cpu().numpy(), ref[0])
+    with pytest.raises(Exception):
+        fresh.set_shapes(H, W, C, nr, 0)
+    fresh.close()

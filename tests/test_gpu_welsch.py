@@ -1,0 +1,127 @@
+"""GPU parity of the Welsch-penalty ILS (Sec. 5, Eqs. (18)-(20)) against the
+FP64 oracle, through the C ABI.  Same bar as the Charbonnier path: max-abs
+<= 1e-4 and relative L2 <= 1e-5 on [0, 1] images."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import ils as O
+from synth import clipart_image, texture_image, voronoi_image
+
+pytestmark = pytest.mark.gpu
+
+MAX_ABS = 1e-4
+REL_L2 = 1e-5
+
+
+def _say(msg):
+    print(f"[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    if not _t.cuda.is_available():
+        pytest.skip("no GPU")
+    return _t
+
+
+@pytest.fixture(scope="module")
+def ils(torch):
+    from paper_2003_07504_amd import ils as m
+    return m
+
+
+def _errs(u_gpu, u_ref):
+    d = u_gpu.astype(np.float64) - u_ref
+    return float(np.max(np.abs(d))), float(np.linalg.norm(d) / np.linalg.norm(u_ref))
+
+
+# (H, W, C, lambda, gamma, N, image kind): the paper's clip-art (lambda = 20,
+# gamma = 10/255, N = 10) and texture (lambda = 30, gamma = 10/255, N = 15)
+# settings at the nearest compiled sizes, plus small and ragged shapes.
+CASES = [
+    (8, 8, 1, 20.0, 10 / 255, 10, "clipart"),
+    (64, 96, 1, 20.0, 10 / 255, 10, "clipart"),
+    (90, 120, 3, 30.0, 5 / 255, 10, "clipart"),
+    (256, 256, 1, 30.0, 10 / 255, 15, "texture"),
+    (540, 1024, 3, 20.0, 10 / 255, 10, "clipart"),
+    (480, 640, 3, 30.0, 10 / 255, 15, "texture"),
+    (1080, 1920, 1, 1.0, 0.05, 4, "voronoi"),
+]
+
+
+def _image(kind, H, W, C, seed):
+    if kind == "clipart":
+        return clipart_image(H, W, C, K=max(4, H * W // 8000), seed=seed)
+    if kind == "texture":
+        return texture_image(H, W, C, K=max(4, H * W // 10000), seed=seed)
+    return voronoi_image(H, W, C, 400, 0.05, seed=seed)
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"{c[0]}x{c[1]}x{c[2]}_N{c[5]}" for c in CASES])
+def test_welsch_parity(torch, ils, case):
+    H, W, C, lam, gam, N, kind = case
+    _say(f"welsch H={H} W={W} C={C} lam={lam} gamma={gam:.4f} N={N} {kind}")
+    f = _image(kind, H, W, C, seed=H + W + C)
+    ref = O.ils_welsch(f.astype(np.float64), lam, gam, N)
+    plan = ils.Plan(H, W, C)
+    u = plan.smooth_welsch(torch.from_numpy(f).cuda(), lam, gam, N)
+    torch.cuda.synchronize()
+    assert plan.last_error() == 0
+    mx, rel = _errs(u.cpu().numpy(), ref)
+    _say(f"  max-abs {mx:.2e} rel-L2 {rel:.2e}")
+    assert mx <= MAX_ABS and rel <= REL_L2, (mx, rel)
+    plan.close()
+
+
+def test_welsch_trivial_cases_copy(torch, ils):
+    f = clipart_image(64, 64, 1, seed=3)
+    ft = torch.from_numpy(f).cuda()
+    plan = ils.Plan(64, 64, 1)
+    for lam, N in ((0.0, 10), (20.0, 0)):
+        u = plan.smooth_welsch(ft, lam, 10 / 255, N)
+        torch.cuda.synchronize()
+        assert np.array_equal(u.cpu().numpy(), f)
+    with pytest.raises(Exception):
+        plan.smooth_welsch(ft, 20.0, 0.0, 10)
+    with pytest.raises(Exception):
+        plan.smooth_welsch(ft, 20.0, float("nan"), 10)
+    plan.close()
+
+
+def test_welsch_constant_image_is_fixed(torch, ils):
+    f = np.full((1, 90, 120), 0.37, dtype=np.float32)
+    plan = ils.Plan(90, 120, 1)
+    u = plan.smooth_welsch(torch.from_numpy(f).cuda(), 30.0, 10 / 255, 15)
+    torch.cuda.synchronize()
+    assert np.max(np.abs(u.cpu().numpy() - 0.37)) < 1e-6
+    plan.close()
+
+
+def test_batch_mixes_penalties(torch, ils):
+    """Charbonnier and Welsch frames of one size in one batched call: each
+    frame equals its single-frame result bit for bit, on eager calls and on
+    graph replays."""
+    H, W, C = 540, 1024, 3
+    fs = [torch.from_numpy(clipart_image(H, W, C, seed=10 + i)).cuda() for i in range(4)]
+    frames = [ils.Welsch(fs[0], 20.0, 10 / 255, 10), (fs[1], 1.0, 0.8, 1e-4, 4),
+              ils.Welsch(fs[2], 30.0, 5 / 255, 10), (fs[3], 2.0, 0.5, 1e-4, 10)]
+    single_plan = ils.Plan(H, W, C)
+    want = [single_plan.smooth_welsch(fs[0], 20.0, 10 / 255, 10).cpu().numpy(),
+            single_plan.smooth(fs[1], 1.0, 0.8, 1e-4, 4).cpu().numpy(),
+            single_plan.smooth_welsch(fs[2], 30.0, 5 / 255, 10).cpu().numpy(),
+            single_plan.smooth(fs[3], 2.0, 0.5, 1e-4, 10).cpu().numpy()]
+    single_plan.close()
+    for graph in (False, True):
+        plan = ils.Plan(H, W, C, max_frames=4, graph=graph)
+        for rep in range(3):
+            outs = plan.smooth_batch(frames)
+            torch.cuda.synchronize()
+            assert plan.last_error() == 0
+            for i, o in enumerate(outs):
+                assert np.array_equal(o.cpu().numpy(), want[i]), (graph, rep, i)
+            _ = torch.ones(1024, device="cuda").sum()  # eager work between replays
+        plan.close()

@@ -326,3 +326,28 @@ def test_oracle_regression_fixture():
     f = np.array(g["f"], dtype=np.float64)
     u = O.ils(f, g["lam"], g["p"], g["eps"], g["N"])
     assert np.max(np.abs(u - np.array(g["u"]))) < 1e-13
+
+
+def test_welsch_channels_are_independent():
+    """A (C, H, W) stack is smoothed channel by channel (Sec. 3.4)."""
+    from synth import clipart_image
+    f = clipart_image(16, 24, 2, K=5, seed=4).astype(np.float64)
+    u = O.ils_welsch(f, 20.0, 10 / 255, 3)
+    for ch in range(2):
+        assert np.array_equal(u[ch], O.ils_welsch(f[ch], 20.0, 10 / 255, 3))
+
+
+def test_welsch_large_gamma_tends_to_quadratic():
+    """For gamma >> |grad u| the Welsch penalty is ~ x^2 (phi_W = 2 g^2 (1 -
+    exp(-x^2/2g^2)) -> x^2), so one step from u0 = f approaches the L2
+    (p = 2) smoother, whose solution is the closed-form Fourier filter
+    F(f) / (1 + lam (Sx + Sy))."""
+    rng = np.random.default_rng(5)
+    f = rng.random((12, 16)) * 0.01
+    lam = 3.0
+    H, W = f.shape
+    ky = 4 * np.sin(np.pi * np.arange(H) / H) ** 2
+    kx = 4 * np.sin(np.pi * np.arange(W) / W) ** 2
+    closed = np.real(np.fft.ifft2(np.fft.fft2(f) / (1 + lam * (ky[:, None] + kx[None, :]))))
+    u = O.ils_welsch(f, lam, 1e3, 200)
+    assert np.max(np.abs(u - closed)) < 1e-7
