@@ -284,6 +284,8 @@ def main():
     say(f"warmup {args.warmup} steps")
     run(0, args.warmup)
     torch.cuda.synchronize()
+    shapes = dict(zip(("row_shape", "col_shape"), plan.tune(H, W, C)))
+    say(f"tile shapes chosen by the tuner: {shapes} of {ils.shape_variants(H, W)}")
     say(f"timed region {args.steps} steps")
     # ---- timed region
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -389,6 +391,7 @@ def main():
         "gpu_event_ms": round(gpu_ms, 4),
         "roofline": roofline,
         "passes": per_kind,
+        "tile_shapes": shapes,
         "cpu_baseline": cpu,
         "extras": extras,
     }

@@ -165,9 +165,9 @@ int ils_profile_end(ils_plan* plan, double* total_ms, int* count);
 int ils_last_error(ils_plan* plan);
 
 /* ---- tile shapes (the autotuner) ----
- * Transform lengths of 480 and more are compiled with two row-band heights
- * (rows per workgroup of the row passes) and two column-tile widths
- * (spectrum columns per workgroup of the column pass).  Every shape runs the
+ * Transform lengths of 480 and more are compiled with up to four row-band
+ * heights (rows per workgroup of the row passes) and up to four column-tile
+ * widths (spectrum columns per workgroup of the column pass).  Every shape runs the
  * same arithmetic on every row and column, so the results are bitwise equal;
  * only the speed differs.  The first smoothing call for a size H x W x C
  * times the shapes on the plan's stream (a few launches on workspace data,
@@ -175,10 +175,11 @@ int ils_last_error(ils_plan* plan);
  * A call made while the stream is being captured into a graph keeps the
  * default shapes and leaves the size untuned.  Environment: ILS_TUNE=0
  * keeps the defaults; ILS_TUNE_CACHE=<file> reads earlier choices at plan
- * creation ("arch H W C row col" per line) and appends new ones.
+ * creation ("arch H W C rows-per-band columns-per-tile" per line) and
+ * appends new ones.
  *
  * ils_shape_variants: number of row / column shapes for a supported size
- *   (each 1 or 2).  ILS_ERR_UNSUPPORTED_SIZE otherwise.
+ *   (each 1 to 4).  ILS_ERR_UNSUPPORTED_SIZE otherwise.
  * ils_plan_tune: tune the size now if it is not yet (synchronises the
  *   plan's stream) and return the chosen shape indices (0 = default).
  * ils_plan_set_shapes: fix the shapes for a size (indices below the counts

@@ -272,9 +272,18 @@ static void load_tune_cache(ils_plan* plan) {
   FILE* fh = std::fopen(path, "r");
   if (!fh) return;
   char arch[64];
-  int H, W, C, r, c;
-  while (std::fscanf(fh, "%63s %d %d %d %d %d", arch, &H, &W, &C, &r, &c) == 6)
-    if (plan->arch == arch && r >= 0 && r < 2 && c >= 0 && c < 2) plan->tuned[size_key(H, W, C)] = {r, c};
+  int H, W, C, g, sc;
+  while (std::fscanf(fh, "%63s %d %d %d %d %d", arch, &H, &W, &C, &g, &sc) == 6) {
+    if (plan->arch != arch || !find_ops(H) || W < 2 || (W & 1) || !find_ops(W / 2)) continue;
+    const LenOps* orow = find_ops(W / 2);
+    const LenOps* ocol = find_ops(H);
+    int r = -1, c = -1;
+    for (int i = 0; i < orow->nrow; ++i)
+      if (orow->row[i].rows[ilsk::ROW_MID] == g) r = i;
+    for (int i = 0; i < ocol->ncol; ++i)
+      if (ocol->col[i].cols == sc) c = i;
+    if (r >= 0 && c >= 0) plan->tuned[size_key(H, W, C)] = {r, c};
+  }
   std::fclose(fh);
 }
 
@@ -339,7 +348,8 @@ static Pick choose(ils_plan* plan, const FrameDesc& d) {
       if (path) {
         FILE* fh = std::fopen(path, "a");
         if (fh) {
-          std::fprintf(fh, "%s %d %d %d %d %d\n", plan->arch.c_str(), d.H, d.W, d.C, ch.first, ch.second);
+          std::fprintf(fh, "%s %d %d %d %d %d\n", plan->arch.c_str(), d.H, d.W, d.C,
+                       orow->row[ch.first].rows[ilsk::ROW_MID], ocol->col[ch.second].cols);
           std::fclose(fh);
         }
       }

@@ -93,10 +93,11 @@ constexpr int row_band() {
   return g;
 }
 
-// Alternative offered to the tuner: one larger workgroup per CU (fewer halo
-// rows per output row, fewer and larger blocks).
+// Alternatives offered to the tuner: one workgroup per CU with the largest
+// band that fits (fewest halo rows per output row), and bands of about 3/4
+// and 5/8 of it, which split a frame into fewer blocks than CUs more evenly.
 template <int P, int Q>
-constexpr int row_band_alt() {
+constexpr int row_band_max() {
   constexpr int slot = 4 * RowGeom<P, Q>::SLOT_F;
   constexpr int tab = 4 * RowGeom<P, Q>::TAB_F;
   int g = (163840 - tab) / slot - 2;
@@ -104,6 +105,11 @@ constexpr int row_band_alt() {
   while ((g + 2) * RowGeom<P, Q>::T > 1024) --g;
   if (g < 1) g = 1;
   return g;
+}
+template <int P, int Q, int i>
+constexpr int row_band_alt() {
+  constexpr int gm = row_band_max<P, Q>();
+  return i == 0 ? gm : i == 1 ? (3 * gm + 2) / 4 : (5 * gm + 4) / 8;
 }
 
 // Column tile of S spectrum columns.  The exchange row of one k1 is padded
@@ -122,14 +128,17 @@ struct ColGeom {
 // Default column tile: the widest whose exchange and table fit the 160 KB of
 // LDS (16 columns are whole 128-byte lines of the row-major spectrum;
 // narrower tiles make neighbouring blocks fetch the same lines).  The
-// alternative offered to the tuner is the next narrower tile.
+// narrower tiles offered to the tuner trade line efficiency for a grid that
+// spreads more evenly over the compute units.
 template <int P, int Q>
 constexpr int col_tile() {
   return ColGeom<P, Q, 16>::fits ? 16 : ColGeom<P, Q, 8>::fits ? 8 : 4;
 }
-template <int P, int Q>
+template <int P, int Q, int i>
 constexpr int col_tile_alt() {
-  return col_tile<P, Q>() > 4 ? col_tile<P, Q>() / 2 : 4;
+  constexpr int w = col_tile<P, Q>();
+  constexpr int cand[3] = {w == 16 ? 12 : 4, 8, 4};
+  return ColGeom<P, Q, cand[i]>::fits && cand[i] < w ? cand[i] : w;
 }
 
 // exp(+- i pi m / n) as a compile-time complex constant.

@@ -61,4 +61,4 @@ def texture_image(H: int, W: int, C: int = 3, K: int = 30, amp: float = 0.2, sig
     stripes = np.sin(2.0 * np.pi * (xx * np.cos(t) + yy * np.sin(t)) / period[label] + phase[label])
     img = inten[:, label] + amp * stripes[None] + sigma * rng.standard_normal((C, H, W))
     np.clip(img, 0.0, 1.0, out=img)
-    return img.astype(np.float32)
+    return np.ascontiguousarray(img, dtype=np.float32)

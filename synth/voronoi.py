@@ -36,7 +36,7 @@ def voronoi_image(H: int, W: int, C: int = 1, K: int = 40, sigma: float = 0.05,
     img = inten[:, label]
     img = img + sigma * rng.standard_normal((C, H, W))
     np.clip(img, 0.0, 1.0, out=img)
-    return img.astype(np.float32)
+    return np.ascontiguousarray(img, dtype=np.float32)
 
 
 @dataclass(frozen=True)

@@ -351,3 +351,10 @@ def test_welsch_large_gamma_tends_to_quadratic():
     closed = np.real(np.fft.ifft2(np.fft.fft2(f) / (1 + lam * (ky[:, None] + kx[None, :]))))
     u = O.ils_welsch(f, lam, 1e3, 200)
     assert np.max(np.abs(u - closed)) < 1e-7
+
+
+def test_generators_return_contiguous_float32():
+    from synth import clipart_image, texture_image, voronoi_image
+    for img in (voronoi_image(30, 40, 3, 5, seed=1), clipart_image(30, 40, 3, K=5, seed=1),
+                texture_image(30, 40, 3, K=5, seed=1)):
+        assert img.dtype == np.float32 and img.flags["C_CONTIGUOUS"] and img.shape == (3, 30, 40)
