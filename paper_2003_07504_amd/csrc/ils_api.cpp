@@ -264,7 +264,11 @@ struct Pick {
   const ColVariant* cv;
 };
 
-static long long size_key(int H, int W, int C) { return ((long long)H << 32) | ((long long)W << 8) | C; }
+// H and W stay below 2^16 (compiled lengths); C counts every channel of a
+// batch class.
+static long long size_key(int H, int W, int C) {
+  return ((long long)H << 48) | ((long long)W << 32) | (long long)(unsigned)C;
+}
 
 static void load_tune_cache(ils_plan* plan) {
   const char* path = std::getenv("ILS_TUNE_CACHE");
@@ -756,7 +760,16 @@ int ils_smooth_batch(ils_plan* plan, const ils_frame* frames, int n) {
   std::vector<size_t> offs;  // (desc, row starts, fin starts, col starts) per class
   for (const Class& cl : classes) {
     Launch L;
-    L.pk = choose(plan, descs[cl.idx[0]]);
+    // shapes are tuned for the class's whole work (all channels of all its
+    // frames), timed on a stand-in frame with that many channels laid out
+    // over the class's share of the workspace
+    FrameDesc tdesc = descs[cl.idx[0]];
+    int ctot = 0;
+    for (int i : cl.idx) ctot += descs[i].C;
+    tdesc.C = ctot;
+    tdesc.specA = reinterpret_cast<cf*>(base);
+    tdesc.specB = reinterpret_cast<cf*>(base + (size_t)ctot * tdesc.H * tdesc.ldS * sizeof(cf));
+    L.pk = choose(plan, tdesc);
     L.N = cl.N;
     L.pen = cl.pen;
     std::vector<FrameDesc> cd;

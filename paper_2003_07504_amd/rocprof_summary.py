@@ -37,20 +37,39 @@ def kind_of(name: str) -> str:
 
 
 def trace(db):
+    """Per pass kind, the kernel instance launched most often (the tuner also
+    times the other tile shapes a few times) with its duration statistics."""
     con = sqlite3.connect(db)
     rows = con.execute("select name, count(*), avg(duration), min(duration), max(duration) "
                        "from kernels group by name").fetchall()
-    return {kind_of(n): (n, c, a / 1e3, lo / 1e3, hi / 1e3) for n, c, a, lo, hi in rows}
+    out = {}
+    for n, c, a, lo, hi in rows:
+        k = kind_of(n)
+        if k not in out or c > out[k][1]:
+            out[k] = (n, c, a / 1e3, lo / 1e3, hi / 1e3)
+    return out
 
 
 def counters(db):
+    """{kernel name: {counter: average value per dispatch}}."""
     con = sqlite3.connect(db)
     rows = con.execute("select kernel_name, counter_name, avg(value) from counters_collection "
                        "group by kernel_name, counter_name").fetchall()
     d = collections.defaultdict(dict)
     for kn, cn, v in rows:
-        d[kind_of(kn)][cn] = v
+        d[kn][cn] = v
     return d
+
+
+def by_kind(cnt, kt, kind):
+    """Counters of the kernel instance the trace chose for this kind (the copy
+    reference is looked up by kind)."""
+    if kind in kt and kt[kind][0] in cnt:
+        return cnt[kt[kind][0]]
+    for name, v in cnt.items():
+        if kind_of(name) == kind:
+            return v
+    return {}
 
 
 def main():
@@ -69,8 +88,8 @@ def main():
     fe = counters(a.fetch)
     wr = counters(a.write)
     sq = counters(a.sq) if a.sq else {}
-    fscale = COPY_BYTES / (fe["copy"]["FETCH_SIZE"] * 1024.0)
-    wscale = COPY_BYTES / (wr["copy"]["WRITE_SIZE"] * 1024.0)
+    fscale = COPY_BYTES / (by_kind(fe, kt, "copy")["FETCH_SIZE"] * 1024.0)
+    wscale = COPY_BYTES / (by_kind(wr, kt, "copy")["WRITE_SIZE"] * 1024.0)
     H, W, C = (int(v) for v in a.size.split("x"))
     img = C * H * W * 4
     spec = C * H * (W // 2 + 1) * 8
@@ -88,8 +107,8 @@ def main():
         if k not in kt:
             continue
         name, calls, avg, lo, hi = kt[k]
-        rd = fe.get(k, {}).get("FETCH_SIZE", 0.0) * 1024 * fscale
-        wb = wr.get(k, {}).get("WRITE_SIZE", 0.0) * 1024 * wscale
+        rd = by_kind(fe, kt, k).get("FETCH_SIZE", 0.0) * 1024 * fscale
+        wb = by_kind(wr, kt, k).get("WRITE_SIZE", 0.0) * 1024 * wscale
         lines.append(f"{k:10s} {calls:5d} {avg:8.3f} {lo:8.3f} {hi:8.3f} {alg[k] / 1e6:8.2f} {(rd + wb) / 1e6:8.2f} "
                      f"{rd / 1e6:8.2f} {wb / 1e6:8.2f} {alg[k] / (avg * 1e3):9.1f} {(rd + wb) / (avg * 1e3):9.1f}")
         traffic[f"{k}@{a.size}"] = {"bytes_per_launch": int(rd + wb), "read_bytes": int(rd), "write_bytes": int(wb),
@@ -97,9 +116,10 @@ def main():
     if sq:
         lines += ["", "SQ counters per launch (SQ_INSTS_* and SQ_WAVES per dispatch; cycles summed over SQs):"]
         for k in ("row_first", "row_mid", "column", "row_final"):
-            if k in sq:
-                lines.append(f"  {k}: " + ", ".join(f"{cn}={v:.0f}" for cn, v in sorted(sq[k].items())))
-                traffic.setdefault(f"{k}@{a.size}", {})["sq"] = {cn: v for cn, v in sq[k].items()}
+            sk = by_kind(sq, kt, k)
+            if sk:
+                lines.append(f"  {k}: " + ", ".join(f"{cn}={v:.0f}" for cn, v in sorted(sk.items())))
+                traffic.setdefault(f"{k}@{a.size}", {})["sq"] = dict(sk)
     with open(a.out, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     with open(a.traffic, "w") as fh:
