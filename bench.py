@@ -243,6 +243,48 @@ def stress_4k_figures(say, reps=2, distinct=8):
             "distinct_frames": distinct}
 
 
+def application_figures(ring, say, reps=32):
+    """Per-frame time of the applications on the 1080p RGB ring (luminance-only
+    smoothing, detail enhancement k = 3) and of the Welsch-penalty smoother at
+    the paper's clip-art (lambda 20, gamma 10/255, N 10) and texture (lambda 30,
+    gamma 10/255, N 15) settings on the nearest compiled sizes."""
+    import torch
+
+    from paper_2003_07504_amd import ils
+    from synth import clipart_image, texture_image
+
+    def per_frame(fn, n):
+        for i in range(2):
+            fn(i)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for i in range(n):
+            fn(i)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - a) / n
+
+    res = {}
+    C, H, W = ring[0].shape
+    plan = ils.Plan(H, W, C)
+    out = torch.empty_like(ring[0])
+    t = per_frame(lambda i: plan.smooth_luminance(ring[i % len(ring)], 1.0, 0.8, 1e-4, 4, 0.0, out=out), reps)
+    res["luminance_only_1080p_rgb_n4"] = {"ms_per_frame": round(t * 1e3, 4), "Mpixel_s": round(H * W / t / 1e6, 1)}
+    t = per_frame(lambda i: plan.detail_enhance(ring[i % len(ring)], 1.0, 0.8, 1e-4, 4, 3.0, out=out), reps)
+    res["detail_enhance_k3_1080p_rgb_n4"] = {"ms_per_frame": round(t * 1e3, 4), "Mpixel_s": round(H * W / t / 1e6, 1)}
+    plan.close()
+    for name, (Hh, Ww, lam, gam, N, img) in {
+            "welsch_clipart_540x1024_rgb_n10": (540, 1024, 20.0, 10 / 255, 10, clipart_image(540, 1024, 3, seed=7)),
+            "welsch_texture_480x640_rgb_n15": (480, 640, 30.0, 10 / 255, 15, texture_image(480, 640, 3, seed=8))}.items():
+        ft = torch.from_numpy(img).cuda()
+        o = torch.empty_like(ft)
+        pw = ils.Plan(Hh, Ww, 3)
+        t = per_frame(lambda i: pw.smooth_welsch(ft, lam, gam, N, out=o), reps)
+        res[name] = {"ms_per_frame": round(t * 1e3, 4), "fps": round(1 / t, 1)}
+        pw.close()
+    say(f"applications: {res}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -361,6 +403,8 @@ def main():
                                       "Mpixel_s": round(H * W / bt / 1e6, 1)}
         say("uneven-size batch of 64 frames")
         extras["batch_mix_64"] = batch_mix_figures(say)
+        say("applications (luminance mode, detail enhancement, Welsch penalty)")
+        extras["applications"] = application_figures(ring, say)
         say("4K RGB N=10 stress batch of 32 frames")
         extras["stress_4k_n10_32"] = stress_4k_figures(say)
         if os.path.exists(args.weights):

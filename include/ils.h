@@ -130,6 +130,38 @@ int ils_smooth(ils_plan* plan, const float* f, int H, int W, int C, float lambda
 int ils_smooth_welsch(ils_plan* plan, const float* f, int H, int W, int C, float lambda, float gamma,
                       int N, float* out);
 
+/* Detail enhancement (Sec. 4, the application the paper's figures show with
+ * details boosted k = 3 times): out = u + k (f - u), u = u^N of ils_smooth.
+ * The blend is fused into the final row pass (one extra read of f).
+ * k finite; k = 0 gives ils_smooth, k = 1 gives f.  Other rules as
+ * ils_smooth (out == f allowed). */
+int ils_detail_enhance(ils_plan* plan, const float* f, int H, int W, int C, float lambda, float p,
+                       float eps, int N, float k, float* out);
+
+/* Luminance-only colour mode (Sec. 3.4, option (I)): for a planar RGB frame
+ * (3 x H x W) smooth only Y = 0.299 R + 0.587 G + 0.114 B and add the change
+ * of Y back to each channel, out_c = f_c + (v - Y) with v = u + k (Y - u)
+ * (k = 0: plain smoothing; k > 0: detail enhancement of the luminance).
+ * This is a YUV round trip that leaves U and V unchanged.  About a third of
+ * the work of smoothing the three channels.  The workspace must hold
+ * ils_luminance_workspace_bytes(H, W) (a plan for 3 channels always does).
+ * out == f allowed. */
+size_t ils_luminance_workspace_bytes(int max_H, int max_W);
+int ils_smooth_luminance(ils_plan* plan, const float* f, int H, int W, float lambda, float p, float eps,
+                         int N, float k, float* out);
+
+/* Energy of Eq. (1), E(u) = sum (u - f)^2 + lambda sum (phi(D_x u) +
+ * phi(D_y u)) over all pixels and channels, periodic differences, computed
+ * in double: phi = (x^2 + eps)^(p/2) (Eq. (2)) for ils_energy, the Welsch
+ * penalty 2 gamma^2 (1 - exp(-x^2 / (2 gamma^2))) (Eq. (18)) for
+ * ils_energy_welsch.  f, u: device C x H x W float32; energy: device double,
+ * written on the plan's stream.  For convergence studies (energy against the
+ * iteration number). */
+int ils_energy(ils_plan* plan, const float* f, const float* u, int H, int W, int C, float lambda, float p,
+               float eps, double* energy);
+int ils_energy_welsch(ils_plan* plan, const float* f, const float* u, int H, int W, int C, float lambda,
+                      float gamma, double* energy);
+
 /* As ils_smooth but starting from u^0 = u0 while the data term stays f
  * (N iterations of Eq. (7)-(9)).  With N = 1 this is the one-iteration map
  * T(u0) used to judge a candidate output by its fixed-point residual.

@@ -47,7 +47,8 @@ __all__ = [
     "phi_p", "dphi_p", "charbonnier_c0", "grad_x", "grad_y", "mu_update",
     "transfer_functions", "fft_solve", "ils", "ils_channels", "energy",
     "dense_ls_step", "fixed_point_residual", "phi_welsch", "dphi_welsch",
-    "welsch_c0", "mu_update_welsch", "ils_welsch",
+    "welsch_c0", "mu_update_welsch", "ils_welsch", "energy_welsch",
+    "luma", "ils_luminance", "detail_enhance",
 ]
 
 
@@ -292,3 +293,45 @@ def ils_welsch(f, lam, gamma, N=10, workers=None):
         mu_y = mu_update_welsch(grad_y(u), gamma, c)
         u = fft_solve(f, mu_x, mu_y, lam, c, tf=tf, workers=workers)
     return u
+
+
+def energy_welsch(u, f, lam, gamma):
+    """E(u, f) of Eq. (1) with the Welsch penalty of Eq. (18) in place of
+    phi_p (the objective the Sec. 5 iteration decreases)."""
+    u = np.asarray(u, dtype=np.float64)
+    f = np.asarray(f, dtype=np.float64)
+    return float(np.sum((u - f) ** 2)
+                 + lam * (np.sum(phi_welsch(grad_x(u), gamma))
+                          + np.sum(phi_welsch(grad_y(u), gamma))))
+
+
+# --------------------------------------------------------------------------
+# Applications (Sec. 3.4 colour handling, Sec. 4 detail enhancement)
+# --------------------------------------------------------------------------
+LUMA = (0.299, 0.587, 0.114)  # BT.601 luma weights (the Y of YUV)
+
+
+def luma(f):
+    """Y = 0.299 R + 0.587 G + 0.114 B of a (3, H, W) frame."""
+    f = np.asarray(f, dtype=np.float64)
+    return LUMA[0] * f[0] + LUMA[1] * f[1] + LUMA[2] * f[2]
+
+
+def detail_enhance(f, u, k):
+    """Details f - u boosted k times on top of the smoothed image: u + k (f - u)."""
+    f = np.asarray(f, dtype=np.float64)
+    u = np.asarray(u, dtype=np.float64)
+    return u + k * (f - u)
+
+
+def ils_luminance(f, lam, p, eps=1e-4, N=4, k=0.0, workers=None):
+    """Sec. 3.4 option (I): go to YUV, smooth (and optionally enhance) only
+    Y, come back with U and V unchanged.  The inverse YUV transform adds the
+    same multiple (1) of Y to R, G and B, so each channel receives the change
+    of Y: out_c = f_c + (v - Y), v = Y's smoothed (enhanced) version."""
+    f = np.asarray(f, dtype=np.float64)
+    if f.ndim != 3 or f.shape[0] != 3:
+        raise ValueError("ils_luminance expects a (3, H, W) RGB frame")
+    y = luma(f)
+    v = detail_enhance(y, ils(y, lam, p, eps, N, workers=workers), k)
+    return f + (v - y)[None]

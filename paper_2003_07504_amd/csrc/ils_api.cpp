@@ -218,6 +218,7 @@ static void fill_desc(const ils_plan* plan, FrameDesc& d, int H, int W, int C, f
   d.a_exp = (float)((double)p / 2.0 - 1.0);
   d.inv_eps = (float)(1.0 / (double)eps);
   d.col_scale = (float)(1.0 / (2.0 * (double)H * (double)W));
+  d.boost = 0.0f;
 }
 
 // Welsch penalty (Sec. 5): c = c0 = 2 (Eq. (20)), so kappa = lambda; the
@@ -249,6 +250,11 @@ static int col_items(const ColVariant* v, const FrameDesc& d) {
   const int s = v->cols;
   return d.C * ((d.W / 2 + 1 + s - 1) / s);
 }
+
+// Elementwise kernels of the luminance mode (ils_apps.hip).
+hipError_t ilsk_launch_luma(const float* rgb, float* y, long long plane, hipStream_t st);
+hipError_t ilsk_launch_recombine(const float* f, const float* y, const float* v, float* out, long long plane,
+                                 hipStream_t st);
 
 // ---------------------------------------------------------------- tuner
 // Lengths of 480 and more offer two row-band and two column-tile shapes.
@@ -673,6 +679,70 @@ int ils_smooth_welsch(ils_plan* plan, const float* f, int H, int W, int C, float
   d.specA = reinterpret_cast<cf*>(base);
   d.specB = reinterpret_cast<cf*>(base + (size_t)C * H * d.ldS * sizeof(cf));
   return run_frame(plan, d, N, ilsk::PEN_WELSCH);
+}
+
+int ils_detail_enhance(ils_plan* plan, const float* f, int H, int W, int C, float lambda, float p, float eps,
+                       int N, float k, float* out) {
+  if (!plan || !f || !out || !finite_f(k)) return ILS_ERR_INVALID_ARG;
+  int rc = check_params(lambda, p, eps, N);
+  if (rc != ILS_OK) return rc;
+  rc = check_size(plan, H, W, C);
+  if (rc != ILS_OK) return rc;
+  const size_t need = frame_ws_bytes(H, W, C);
+  if (plan->ws_bytes < kBatchHeaderBytes + need) return ILS_ERR_WORKSPACE;
+  if (N == 0 || lambda == 0.0f) {  // u = f, so u + k (f - u) = f
+    if (f == out) return ILS_OK;
+    return record(plan, hipMemcpyAsync(out, f, (size_t)C * H * W * sizeof(float), hipMemcpyDeviceToDevice,
+                                       plan->stream));
+  }
+  FrameDesc d;
+  fill_desc(plan, d, H, W, C, lambda, p, eps);
+  d.f = f;
+  d.u0 = f;
+  d.out = out;
+  d.boost = k;
+  char* base = plan->ws + kBatchHeaderBytes;
+  d.specA = reinterpret_cast<cf*>(base);
+  d.specB = reinterpret_cast<cf*>(base + (size_t)C * H * d.ldS * sizeof(cf));
+  return run_frame(plan, d, N);
+}
+
+size_t ils_luminance_workspace_bytes(int max_H, int max_W) {
+  if (max_H < 2 || max_W < 2 || (max_W & 1)) return 0;
+  return kBatchHeaderBytes + frame_ws_bytes(max_H, max_W, 1) + 2 * align_up((size_t)max_H * max_W * sizeof(float), 256);
+}
+
+int ils_smooth_luminance(ils_plan* plan, const float* f, int H, int W, float lambda, float p, float eps, int N,
+                         float k, float* out) {
+  if (!plan || !f || !out || !finite_f(k)) return ILS_ERR_INVALID_ARG;
+  int rc = check_params(lambda, p, eps, N);
+  if (rc != ILS_OK) return rc;
+  rc = check_size(plan, H, W, 1);
+  if (rc != ILS_OK) return rc;
+  if (plan->ws_bytes < ils_luminance_workspace_bytes(H, W)) return ILS_ERR_WORKSPACE;
+  const long long plane = (long long)H * W;
+  char* base = plan->ws + kBatchHeaderBytes;
+  const size_t spec = frame_ws_bytes(H, W, 1);
+  float* Y = reinterpret_cast<float*>(base + spec);
+  float* V = reinterpret_cast<float*>(base + spec + align_up((size_t)plane * sizeof(float), 256));
+  hipError_t e = ilsk_launch_luma(f, Y, plane, plan->stream);
+  if (e != hipSuccess) return record(plan, e);
+  if (N == 0 || lambda == 0.0f) {  // u = Y: the output is the input
+    if (f == out) return ILS_OK;
+    return record(plan, hipMemcpyAsync(out, f, 3 * (size_t)plane * sizeof(float), hipMemcpyDeviceToDevice,
+                                       plan->stream));
+  }
+  FrameDesc d;
+  fill_desc(plan, d, H, W, 1, lambda, p, eps);
+  d.f = Y;
+  d.u0 = Y;
+  d.out = V;
+  d.boost = k;  // V = u + k (Y - u)
+  d.specA = reinterpret_cast<cf*>(base);
+  d.specB = reinterpret_cast<cf*>(base + (size_t)H * d.ldS * sizeof(cf));
+  rc = run_frame(plan, d, N);
+  if (rc != ILS_OK) return rc;
+  return record(plan, ilsk_launch_recombine(f, Y, V, out, plane, plan->stream));
 }
 
 int ils_smooth_batch(ils_plan* plan, const ils_frame* frames, int n) {

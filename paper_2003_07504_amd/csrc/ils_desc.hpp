@@ -30,6 +30,8 @@ struct FrameDesc {
   float inv_eps;    // 1 / eps (Welsch: unused)
   float col_scale;  // 1 / (2 H W): inverse-transform normalisation (and the
                     // factor 2 the row R2C leaves in its output)
+  float boost;      // final pass writes u + boost (f - u) when non-zero
+                    // (detail enhancement); 0 writes u
 };
 
 enum RowMode : int { ROW_FIRST = 0, ROW_MID = 1, ROW_FINAL = 2 };

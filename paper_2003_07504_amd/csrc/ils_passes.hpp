@@ -434,10 +434,20 @@ __device__ __forceinline__ void row_final_body(const FrameDesc& d, int band, int
     cf z[P];
     c2r_stage_b<P, Q>(slc, lane, z);
     float2* orow = reinterpret_cast<float2*>(d.out + (size_t)ch * H * W + (size_t)yrow * W);
-    static_for<P>([&](auto n1c) {
-      constexpr int n1 = decltype(n1c)::value;
-      orow[Q * n1 + lane] = make_float2(z[n1].x, z[n1].y);
-    });
+    const float k = d.boost;
+    if (k != 0.0f) {  // detail enhancement: u + k (f - u); each element is read before it is written
+      const float2* frow = reinterpret_cast<const float2*>(d.f + (size_t)ch * H * W + (size_t)yrow * W);
+      static_for<P>([&](auto n1c) {
+        constexpr int n1 = decltype(n1c)::value;
+        const float2 fv = frow[Q * n1 + lane];
+        orow[Q * n1 + lane] = make_float2(fmaf(k, fv.x - z[n1].x, z[n1].x), fmaf(k, fv.y - z[n1].y, z[n1].y));
+      });
+    } else {
+      static_for<P>([&](auto n1c) {
+        constexpr int n1 = decltype(n1c)::value;
+        orow[Q * n1 + lane] = make_float2(z[n1].x, z[n1].y);
+      });
+    }
   }
 }
 

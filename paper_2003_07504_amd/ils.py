@@ -142,6 +142,59 @@ class Plan:
               "ils_smooth_welsch")
         return out
 
+    def detail_enhance(self, f: torch.Tensor, lam: float, p: float, eps: float = 1e-4, N: int = 4, k: float = 3.0,
+                       out: torch.Tensor | None = None) -> torch.Tensor:
+        """u + k (f - u) with u = u^N of Algorithm 1 (blend fused into the final pass)."""
+        fc = _as_chw(f, "f")
+        out = torch.empty_like(f) if out is None else out
+        oc = _as_chw(out, "out")
+        if oc.shape != fc.shape:
+            raise ValueError("out must have the shape of f")
+        C, H, W = fc.shape
+        self._bind_stream()
+        check(self._lib.ils_detail_enhance(self._h, ctypes.c_void_p(fc.data_ptr()), H, W, C, float(lam), float(p),
+                                           float(eps), int(N), float(k), ctypes.c_void_p(oc.data_ptr())),
+              "ils_detail_enhance")
+        return out
+
+    def smooth_luminance(self, f: torch.Tensor, lam: float, p: float, eps: float = 1e-4, N: int = 4,
+                         k: float = 0.0, out: torch.Tensor | None = None) -> torch.Tensor:
+        """Luminance-only smoothing of a (3, H, W) RGB frame (Sec. 3.4, option I)."""
+        fc = _as_chw(f, "f")
+        if fc.shape[0] != 3:
+            raise ValueError("smooth_luminance needs a (3, H, W) RGB frame")
+        out = torch.empty_like(f) if out is None else out
+        oc = _as_chw(out, "out")
+        if oc.shape != fc.shape:
+            raise ValueError("out must have the shape of f")
+        _, H, W = fc.shape
+        self._bind_stream()
+        check(self._lib.ils_smooth_luminance(self._h, ctypes.c_void_p(fc.data_ptr()), H, W, float(lam), float(p),
+                                             float(eps), int(N), float(k), ctypes.c_void_p(oc.data_ptr())),
+              "ils_smooth_luminance")
+        return out
+
+    def energy(self, f: torch.Tensor, u: torch.Tensor, lam: float, p: float | None = None, eps: float = 1e-4,
+               gamma: float | None = None) -> torch.Tensor:
+        """Eq. (1) energy (float64 GPU scalar tensor): Charbonnier with p, or
+        Welsch when gamma is given."""
+        fc = _as_chw(f, "f")
+        uc = _as_chw(u, "u")
+        if uc.shape != fc.shape:
+            raise ValueError("u must have the shape of f")
+        C, H, W = fc.shape
+        e = torch.empty((), dtype=torch.float64, device=self.device)
+        self._bind_stream()
+        if gamma is not None:
+            check(self._lib.ils_energy_welsch(self._h, ctypes.c_void_p(fc.data_ptr()), ctypes.c_void_p(uc.data_ptr()),
+                                              H, W, C, float(lam), float(gamma), ctypes.c_void_p(e.data_ptr())),
+                  "ils_energy_welsch")
+        else:
+            check(self._lib.ils_energy(self._h, ctypes.c_void_p(fc.data_ptr()), ctypes.c_void_p(uc.data_ptr()),
+                                       H, W, C, float(lam), float(p), float(eps), ctypes.c_void_p(e.data_ptr())),
+                  "ils_energy")
+        return e
+
     def iterate_from(self, f: torch.Tensor, u0: torch.Tensor, lam: float, p: float, eps: float = 1e-4,
                      N: int = 1, out: torch.Tensor | None = None) -> torch.Tensor:
         """N iterations of Eqs. (7)-(9) from u^0 = u0 with data term f."""

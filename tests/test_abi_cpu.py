@@ -192,3 +192,13 @@ def test_frame_struct_layout_matches_c(tmp_path):
 
 def test_welsch_entry_point_rejects_null_plan(L):
     assert L.ils_smooth_welsch(None, None, 8, 8, 1, 20.0, 0.04, 10, None) == -1
+
+
+def test_application_entry_points_reject_bad_arguments(L):
+    assert L.ils_detail_enhance(None, None, 8, 8, 1, 1.0, 0.8, 1e-4, 4, 3.0, None) == -1
+    assert L.ils_smooth_luminance(None, None, 8, 8, 1.0, 0.8, 1e-4, 4, 0.0, None) == -1
+    assert L.ils_energy(None, None, None, 8, 8, 1, 1.0, 0.8, 1e-4, None) == -1
+    assert L.ils_energy_welsch(None, None, None, 8, 8, 1, 1.0, 0.04, None) == -1
+    assert L.ils_luminance_workspace_bytes(1080, 1920) == (1 << 20) + 1080 * 976 * 16 + 2 * 1080 * 1920 * 4
+    assert L.ils_luminance_workspace_bytes(1080, 1921) == 0
+    assert L.ils_luminance_workspace_bytes(1080, 1920) <= L.ils_workspace_bytes(1080, 1920, 3, 1)

@@ -1,0 +1,142 @@
+"""GPU parity of the applications around the smoother against the FP64
+oracle, through the C ABI: detail enhancement (fused into the final pass),
+luminance-only colour mode (Sec. 3.4) and the Eq. (1) energy (Charbonnier
+and Welsch) along the iteration."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import ils as O
+from synth import clipart_image, voronoi_image
+
+pytestmark = pytest.mark.gpu
+
+MAX_ABS = 1e-4
+REL_L2 = 1e-5
+
+
+def _say(msg):
+    print(f"[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    if not _t.cuda.is_available():
+        pytest.skip("no GPU")
+    return _t
+
+
+@pytest.fixture(scope="module")
+def ils(torch):
+    from paper_2003_07504_amd import ils as m
+    return m
+
+
+def _errs(u_gpu, u_ref):
+    d = u_gpu.astype(np.float64) - u_ref
+    return float(np.max(np.abs(d))), float(np.linalg.norm(d) / np.linalg.norm(u_ref))
+
+
+@pytest.mark.parametrize("H,W,C,k", [(64, 96, 1, 3.0), (90, 120, 3, 3.0), (1080, 1920, 3, 3.0), (256, 256, 1, 0.5)])
+def test_detail_enhance_parity(torch, ils, H, W, C, k):
+    _say(f"detail enhance H={H} W={W} C={C} k={k}")
+    f = voronoi_image(H, W, C, max(4, H * W // 5000), 0.05, seed=31 + H)
+    ref = O.detail_enhance(f.astype(np.float64), O.ils_channels(f, 1.0, 0.8, 1e-4, 4), k)
+    plan = ils.Plan(H, W, C)
+    out = plan.detail_enhance(torch.from_numpy(f).cuda(), 1.0, 0.8, 1e-4, 4, k)
+    torch.cuda.synchronize()
+    assert plan.last_error() == 0
+    mx, rel = _errs(out.cpu().numpy(), ref)
+    _say(f"  max-abs {mx:.2e} rel-L2 {rel:.2e}")
+    # k amplifies the smoothing error of u by |1 - k|
+    assert mx <= MAX_ABS * max(1.0, abs(1.0 - k)) and rel <= REL_L2 * max(1.0, abs(1.0 - k)), (mx, rel)
+    plan.close()
+
+
+def test_detail_enhance_k0_is_smooth_and_in_place(torch, ils):
+    f = voronoi_image(90, 120, 2, 10, 0.05, seed=5)
+    ft = torch.from_numpy(f).cuda()
+    plan = ils.Plan(90, 120, 2)
+    a = plan.detail_enhance(ft, 1.0, 0.8, 1e-4, 4, 0.0).cpu().numpy()
+    b = plan.smooth(ft, 1.0, 0.8, 1e-4, 4).cpu().numpy()
+    assert np.array_equal(a, b)
+    g = ft.clone()
+    plan.detail_enhance(g, 1.0, 0.8, 1e-4, 4, 3.0, out=g)
+    want = plan.detail_enhance(ft, 1.0, 0.8, 1e-4, 4, 3.0)
+    torch.cuda.synchronize()
+    assert np.array_equal(g.cpu().numpy(), want.cpu().numpy())
+    plan.close()
+
+
+@pytest.mark.parametrize("H,W,k", [(64, 96, 0.0), (90, 120, 2.0), (1080, 1920, 0.0)])
+def test_luminance_mode_parity(torch, ils, H, W, k):
+    _say(f"luminance mode H={H} W={W} k={k}")
+    f = voronoi_image(H, W, 3, max(4, H * W // 5000), 0.05, seed=41 + H)
+    ref = O.ils_luminance(f, 1.0, 0.8, 1e-4, 4, k=k)
+    plan = ils.Plan(H, W, 3)
+    out = plan.smooth_luminance(torch.from_numpy(f).cuda(), 1.0, 0.8, 1e-4, 4, k)
+    torch.cuda.synchronize()
+    assert plan.last_error() == 0
+    mx, rel = _errs(out.cpu().numpy(), ref)
+    _say(f"  max-abs {mx:.2e} rel-L2 {rel:.2e}")
+    assert mx <= MAX_ABS * max(1.0, abs(1.0 - k)) and rel <= REL_L2 * max(1.0, abs(1.0 - k)), (mx, rel)
+    plan.close()
+
+
+def test_luminance_trivial_and_in_place(torch, ils):
+    f = voronoi_image(64, 64, 3, 8, 0.05, seed=2)
+    ft = torch.from_numpy(f).cuda()
+    plan = ils.Plan(64, 64, 3)
+    for lam, N in ((0.0, 4), (1.0, 0)):
+        out = plan.smooth_luminance(ft, lam, 0.8, 1e-4, N)
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), f)
+    g = ft.clone()
+    plan.smooth_luminance(g, 1.0, 0.8, 1e-4, 4, out=g)
+    want = plan.smooth_luminance(ft, 1.0, 0.8, 1e-4, 4)
+    torch.cuda.synchronize()
+    assert np.array_equal(g.cpu().numpy(), want.cpu().numpy())
+    plan.close()
+
+
+def test_energy_along_iterations_matches_oracle(torch, ils):
+    """E(u^n) for n = 0..6 of the GPU iterates, computed on the GPU (double
+    accumulation of float32 data) and by the oracle on the same float32
+    iterates; and the decrease the majorise-minimise argument guarantees."""
+    H, W, C = 256, 256, 3
+    lam, p, eps = 1.0, 0.8, 1e-4
+    f = voronoi_image(H, W, C, 40, 0.05, seed=0)
+    ft = torch.from_numpy(f).cuda()
+    plan = ils.Plan(H, W, C)
+    u = ft.clone()
+    es = []
+    for n in range(7):
+        e_gpu = float(plan.energy(ft, u, lam, p, eps).cpu())
+        un = u.cpu().numpy().astype(np.float64)
+        e_ref = sum(O.energy(un[c], f[c], lam, p, eps) for c in range(C))
+        assert abs(e_gpu - e_ref) <= 1e-9 * e_ref, (n, e_gpu, e_ref)
+        es.append(e_gpu)
+        u = plan.iterate_from(ft, u, lam, p, eps, 1)
+    assert all(b <= a for a, b in zip(es, es[1:])), es
+    plan.close()
+
+
+def test_energy_welsch_matches_oracle(torch, ils):
+    H, W, C = 90, 120, 3
+    lam, gam = 20.0, 10 / 255
+    f = clipart_image(H, W, C, K=8, seed=12)
+    ft = torch.from_numpy(f).cuda()
+    plan = ils.Plan(H, W, C)
+    es = []
+    for N in (0, 1, 2, 5, 10):
+        u = plan.smooth_welsch(ft, lam, gam, N)
+        e_gpu = float(plan.energy(ft, u, lam, gamma=gam).cpu())
+        un = u.cpu().numpy().astype(np.float64)
+        e_ref = sum(O.energy_welsch(un[c], f[c], lam, gam) for c in range(C))
+        assert abs(e_gpu - e_ref) <= 1e-9 * e_ref, (N, e_gpu, e_ref)
+        es.append(e_gpu)
+    assert all(b <= a * (1 + 1e-7) for a, b in zip(es, es[1:])), es
+    plan.close()

@@ -358,3 +358,74 @@ def test_generators_return_contiguous_float32():
     for img in (voronoi_image(30, 40, 3, 5, seed=1), clipart_image(30, 40, 3, K=5, seed=1),
                 texture_image(30, 40, 3, K=5, seed=1)):
         assert img.dtype == np.float32 and img.flags["C_CONTIGUOUS"] and img.shape == (3, 30, 40)
+
+
+# ---------------------------------------------------------------- applications
+def test_luma_weights_sum_to_one_and_grey_reduces_to_plain():
+    """Y of a grey frame is the grey level, so luminance-only smoothing of a
+    grey RGB frame is plain smoothing of each (equal) channel."""
+    assert abs(sum(O.LUMA) - 1.0) < 1e-15
+    g = np.random.default_rng(6).random((12, 16))
+    f = np.stack([g, g, g])
+    out = O.ils_luminance(f, 1.0, 0.8, 1e-4, 3)
+    ref = O.ils(g, 1.0, 0.8, 1e-4, 3)
+    for ch in range(3):
+        assert np.max(np.abs(out[ch] - ref)) < 1e-12
+
+
+def test_luminance_mode_keeps_chroma():
+    """U and V are functions of f_c - Y alone, and those are unchanged:
+    out_c - Y(out) = f_c - Y(f) for every channel."""
+    f = np.random.default_rng(7).random((3, 10, 12))
+    out = O.ils_luminance(f, 2.0, 0.5, 1e-4, 4, k=2.0)
+    assert np.max(np.abs((out - O.luma(out)[None]) - (f - O.luma(f)[None]))) < 1e-12
+
+
+def test_luminance_mode_smooths_luma_exactly():
+    f = np.random.default_rng(8).random((3, 10, 12))
+    out = O.ils_luminance(f, 1.0, 0.8, 1e-4, 4)
+    assert np.max(np.abs(O.luma(out) - O.ils(O.luma(f), 1.0, 0.8, 1e-4, 4))) < 1e-12
+
+
+def test_detail_enhance_endpoints_and_linearity():
+    rng = np.random.default_rng(9)
+    f, u = rng.random((6, 7)), rng.random((6, 7))
+    assert np.array_equal(O.detail_enhance(f, u, 0.0), u)
+    assert np.max(np.abs(O.detail_enhance(f, u, 1.0) - f)) < 1e-15
+    d3 = O.detail_enhance(f, u, 3.0) - u
+    assert np.max(np.abs(d3 - 3.0 * (f - u))) < 1e-14
+
+
+def test_energy_welsch_matches_direct_sum_and_decreases():
+    """Direct double loop over pixels (periodic neighbours) on a tiny image,
+    then monotone decrease along the Welsch iteration (c = c0 = 2)."""
+    rng = np.random.default_rng(10)
+    f = rng.random((5, 6))
+    u = rng.random((5, 6))
+    lam, gam = 3.0, 0.1
+    H, W = f.shape
+    direct = 0.0
+    for y in range(H):
+        for x in range(W):
+            gx = u[y, (x + 1) % W] - u[y, x]
+            gy = u[(y + 1) % H, x] - u[y, x]
+            direct += (u[y, x] - f[y, x]) ** 2 + lam * sum(
+                2 * gam * gam * (1 - np.exp(-g * g / (2 * gam * gam))) for g in (gx, gy))
+    assert abs(O.energy_welsch(u, f, lam, gam) - direct) < 1e-12 * max(1.0, direct)
+    e = [O.energy_welsch(O.ils_welsch(f, lam, gam, n), f, lam, gam) for n in range(6)]
+    assert all(b <= a + 1e-12 for a, b in zip(e, e[1:]))
+
+
+def test_energy_matches_direct_sum():
+    rng = np.random.default_rng(11)
+    f = rng.random((4, 6))
+    u = rng.random((4, 6))
+    lam, p, eps = 1.5, 0.7, 1e-3
+    H, W = f.shape
+    direct = 0.0
+    for y in range(H):
+        for x in range(W):
+            gx = u[y, (x + 1) % W] - u[y, x]
+            gy = u[(y + 1) % H, x] - u[y, x]
+            direct += (u[y, x] - f[y, x]) ** 2 + lam * ((gx * gx + eps) ** (p / 2) + (gy * gy + eps) ** (p / 2))
+    assert abs(O.energy(u, f, lam, p, eps) - direct) < 1e-12 * direct
