@@ -169,6 +169,13 @@ int ils_energy_welsch(ils_plan* plan, const float* f, const float* u, int H, int
 int ils_iterate_from(ils_plan* plan, const float* f, const float* u0, int H, int W, int C,
                      float lambda, float p, float eps, int N, float* out);
 
+/* As ils_iterate_from with the constant c of Eq. (5) given explicitly
+ * instead of c = c0 = p eps^(p/2 - 1) (Sec. 3.3.3: any c >= c0 keeps the
+ * energy decreasing; smaller c converges faster).  c < c0 (beyond a relative
+ * 1e-6) is ILS_ERR_INVALID_ARG.  For convergence studies. */
+int ils_iterate_from_c(ils_plan* plan, const float* f, const float* u0, int H, int W, int C, float lambda,
+                       float p, float eps, float c, int N, float* out);
+
 /* Smooth n frames of possibly different sizes and parameters in one
  * enqueue: one launch per pass and size class over all its frames, the
  * whole sequence replayed as one HIP graph (unless ILS_PLAN_NO_GRAPH or

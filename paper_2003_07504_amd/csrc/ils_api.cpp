@@ -217,6 +217,7 @@ static void fill_desc(const ils_plan* plan, FrameDesc& d, int H, int W, int C, f
   d.kappa = (float)((double)lambda * c0 / 2.0);
   d.a_exp = (float)((double)p / 2.0 - 1.0);
   d.inv_eps = (float)(1.0 / (double)eps);
+  d.log2_r = 0.0f;
   d.col_scale = (float)(1.0 / (2.0 * (double)H * (double)W));
   d.boost = 0.0f;
 }
@@ -230,6 +231,7 @@ static void fill_desc_welsch(const ils_plan* plan, FrameDesc& d, int H, int W, i
   d.kappa = lambda;
   d.a_exp = (float)(-1.4426950408889634 / (2.0 * g * g));
   d.inv_eps = 0.0f;
+  d.log2_r = 0.0f;
 }
 
 // Single-frame work lists for the three launch shapes of a frame.
@@ -648,6 +650,36 @@ int ils_iterate_from(ils_plan* plan, const float* f, const float* u0, int H, int
   const size_t half = (size_t)C * H * d.ldS * sizeof(cf);
   d.specA = reinterpret_cast<cf*>(base);
   d.specB = reinterpret_cast<cf*>(base + half);
+  return run_frame(plan, d, N);
+}
+
+int ils_iterate_from_c(ils_plan* plan, const float* f, const float* u0, int H, int W, int C, float lambda,
+                       float p, float eps, float c, int N, float* out) {
+  if (!plan || !f || !u0 || !out) return ILS_ERR_INVALID_ARG;
+  int rc = check_params(lambda, p, eps, N);
+  if (rc != ILS_OK) return rc;
+  const double c0 = (double)p * std::pow((double)eps, (double)p / 2.0 - 1.0);  // Eq. (11)
+  if (!finite_f(c) || (double)c < c0 * (1.0 - 1e-6)) return ILS_ERR_INVALID_ARG;
+  rc = check_size(plan, H, W, C);
+  if (rc != ILS_OK) return rc;
+  const size_t need = frame_ws_bytes(H, W, C);
+  if (plan->ws_bytes < kBatchHeaderBytes + need) return ILS_ERR_WORKSPACE;
+  if (N == 0 || lambda == 0.0f) {
+    const float* src = (N == 0) ? u0 : f;
+    if (src == out) return ILS_OK;
+    return record(plan, hipMemcpyAsync(out, src, (size_t)C * H * W * sizeof(float), hipMemcpyDeviceToDevice,
+                                       plan->stream));
+  }
+  FrameDesc d;
+  fill_desc(plan, d, H, W, C, lambda, p, eps);
+  d.kappa = (float)((double)lambda * (double)c / 2.0);
+  d.log2_r = (float)std::log2(c0 / (double)c);
+  d.f = f;
+  d.u0 = u0;
+  d.out = out;
+  char* base = plan->ws + kBatchHeaderBytes;
+  d.specA = reinterpret_cast<cf*>(base);
+  d.specB = reinterpret_cast<cf*>(base + (size_t)C * H * d.ldS * sizeof(cf));
   return run_frame(plan, d, N);
 }
 

@@ -25,9 +25,10 @@ struct FrameDesc {
   const cf* tw_col;   // exp(-2 pi i j / H), j < H
   const float* sy;    // 4 sin^2(pi l / H), l < H
   int H, W, C, ldS;
-  float kappa;      // lambda * c / 2, c = p eps^(p/2 - 1) (Welsch: c = 2)
+  float kappa;      // lambda * c / 2, c >= c0 = p eps^(p/2 - 1) (Welsch: c = 2)
   float a_exp;      // p/2 - 1 (Welsch: -log2(e) / (2 gamma^2))
   float inv_eps;    // 1 / eps (Welsch: unused)
+  float log2_r;     // log2(c0 / c): 0 for the paper's c = c0
   float col_scale;  // 1 / (2 H W): inverse-transform normalisation (and the
                     // factor 2 the row R2C leaves in its output)
   float boost;      // final pass writes u + boost (f - u) when non-zero

@@ -28,31 +28,32 @@ namespace ilsk {
 __device__ __forceinline__ int imax(int a, int b) { return a > b ? a : b; }
 __device__ __forceinline__ int imin(int a, int b) { return a < b ? a : b; }
 
-// Normalised half-quadratic variable  mu / c = g (1 - (1 + g^2/eps)^(p/2 - 1))
-// (Eq. (7) divided by c = p eps^(p/2-1)); base-2 log/exp on the hardware
-// transcendental unit.
-__device__ __forceinline__ float mu_ns(float g, float a_exp, float inv_eps) {
+// Normalised half-quadratic variable  mu / c = g (1 - (c0/c) (1 + g^2/eps)^(p/2 - 1))
+// (Eq. (7) divided by c, c0 = p eps^(p/2-1)); base-2 log/exp on the hardware
+// transcendental unit.  l2r = log2(c0 / c) is 0 for c = c0.
+__device__ __forceinline__ float mu_ns(float g, float a_exp, float inv_eps, float l2r) {
   float t = fmaf(g * g, inv_eps, 1.0f);
-  float pw = __builtin_amdgcn_exp2f(a_exp * __builtin_amdgcn_logf(t));
+  float pw = __builtin_amdgcn_exp2f(fmaf(a_exp, __builtin_amdgcn_logf(t), l2r));
   return fmaf(-g, pw, g);
 }
 
 // Welsch penalty (Sec. 5, Eqs. (18)-(20)): with c = c0 = 2 the normalised
 // variable is mu / c = g (1 - exp(-g^2 / (2 gamma^2))); w = -log2(e) / (2 gamma^2).
-__device__ __forceinline__ float mu_ns_welsch(float g, float w) {
-  return fmaf(-g, __builtin_amdgcn_exp2f(w * (g * g)), g);
+__device__ __forceinline__ float mu_ns_welsch(float g, float w, float l2r) {
+  return fmaf(-g, __builtin_amdgcn_exp2f(fmaf(w, g * g, l2r)), g);
 }
 
 enum Penalty : int { PEN_CHARBONNIER = 0, PEN_WELSCH = 1 };
 
 // mu / c for the penalty of the kernel instance: (a, b) = (p/2 - 1, 1/eps)
-// for the generalised Charbonnier penalty, (w, unused) for Welsch.
+// for the generalised Charbonnier penalty, (w, unused) for Welsch; l2r =
+// log2(c0 / c).
 template <int PEN>
-__device__ __forceinline__ float mu_pen(float g, float a, float b) {
+__device__ __forceinline__ float mu_pen(float g, float a, float b, float l2r) {
   if constexpr (PEN == PEN_WELSCH)
-    return mu_ns_welsch(g, a);
+    return mu_ns_welsch(g, a, l2r);
   else
-    return mu_ns(g, a, b);
+    return mu_ns(g, a, b, l2r);
 }
 
 // Synchronisation inside one row slot.  When a slot lies within one
@@ -321,7 +322,7 @@ __device__ __forceinline__ void row_body(const FrameDesc& d, int band, int ch, f
   if (st_slot) {
     const float2* uc = reinterpret_cast<const float2*>(sl);
     const float2* ud = reinterpret_cast<const float2*>(sl + SLOT_F);
-    const float a_exp = d.a_exp, inv_eps = d.inv_eps, kappa = d.kappa;
+    const float a_exp = d.a_exp, inv_eps = d.inv_eps, kappa = d.kappa, l2r = d.log2_r;
     if (slot >= 1) {
       static_for<P>([&](auto n1c) {
         constexpr int n1 = decltype(n1c)::value;
@@ -329,10 +330,10 @@ __device__ __forceinline__ void row_body(const FrameDesc& d, int band, int ch, f
         const int jm = (j == 0) ? M - 1 : j - 1;
         const int jp = (j == M - 1) ? 0 : j + 1;
         const float2 c = uc[j], dn = ud[j], l = uc[jm], rr = uc[jp];
-        myd[n1] = make_float2(mu_pen<PEN>(dn.x - c.x, a_exp, inv_eps), mu_pen<PEN>(dn.y - c.y, a_exp, inv_eps));
-        const float mxl = mu_pen<PEN>(c.x - l.y, a_exp, inv_eps);
-        const float mx0 = mu_pen<PEN>(c.y - c.x, a_exp, inv_eps);
-        const float mx1 = mu_pen<PEN>(rr.x - c.y, a_exp, inv_eps);
+        myd[n1] = make_float2(mu_pen<PEN>(dn.x - c.x, a_exp, inv_eps, l2r), mu_pen<PEN>(dn.y - c.y, a_exp, inv_eps, l2r));
+        const float mxl = mu_pen<PEN>(c.x - l.y, a_exp, inv_eps, l2r);
+        const float mx0 = mu_pen<PEN>(c.y - c.x, a_exp, inv_eps, l2r);
+        const float mx1 = mu_pen<PEN>(rr.x - c.y, a_exp, inv_eps, l2r);
         r[n1] = {fmaf(kappa, (mxl - mx0) - myd[n1].x, fv[n1].x), fmaf(kappa, (mx0 - mx1) - myd[n1].y, fv[n1].y)};
         // batches of five positions: their LDS reads issue together, while
         // the registers of later positions are not claimed early
@@ -343,7 +344,7 @@ __device__ __forceinline__ void row_body(const FrameDesc& d, int band, int ch, f
         constexpr int n1 = decltype(n1c)::value;
         const int j = Q * n1 + t;
         const float2 c = uc[j], dn = ud[j];
-        myd[n1] = make_float2(mu_pen<PEN>(dn.x - c.x, a_exp, inv_eps), mu_pen<PEN>(dn.y - c.y, a_exp, inv_eps));
+        myd[n1] = make_float2(mu_pen<PEN>(dn.x - c.x, a_exp, inv_eps, l2r), mu_pen<PEN>(dn.y - c.y, a_exp, inv_eps, l2r));
       });
     }
   }

@@ -196,8 +196,9 @@ class Plan:
         return e
 
     def iterate_from(self, f: torch.Tensor, u0: torch.Tensor, lam: float, p: float, eps: float = 1e-4,
-                     N: int = 1, out: torch.Tensor | None = None) -> torch.Tensor:
-        """N iterations of Eqs. (7)-(9) from u^0 = u0 with data term f."""
+                     N: int = 1, out: torch.Tensor | None = None, c: float | None = None) -> torch.Tensor:
+        """N iterations of Eqs. (7)-(9) from u^0 = u0 with data term f (c = c0
+        unless c is given; c >= c0)."""
         fc = _as_chw(f, "f")
         uc = _as_chw(u0, "u0")
         if uc.shape != fc.shape:
@@ -206,6 +207,11 @@ class Plan:
         oc = _as_chw(out, "out")
         C, H, W = fc.shape
         self._bind_stream()
+        if c is not None:
+            check(self._lib.ils_iterate_from_c(self._h, ctypes.c_void_p(fc.data_ptr()), ctypes.c_void_p(uc.data_ptr()),
+                                               H, W, C, float(lam), float(p), float(eps), float(c), int(N),
+                                               ctypes.c_void_p(oc.data_ptr())), "ils_iterate_from_c")
+            return out
         check(self._lib.ils_iterate_from(self._h, ctypes.c_void_p(fc.data_ptr()), ctypes.c_void_p(uc.data_ptr()),
                                          H, W, C, float(lam), float(p), float(eps), int(N),
                                          ctypes.c_void_p(oc.data_ptr())), "ils_iterate_from")

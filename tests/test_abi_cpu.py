@@ -202,3 +202,7 @@ def test_application_entry_points_reject_bad_arguments(L):
     assert L.ils_luminance_workspace_bytes(1080, 1920) == (1 << 20) + 1080 * 976 * 16 + 2 * 1080 * 1920 * 4
     assert L.ils_luminance_workspace_bytes(1080, 1921) == 0
     assert L.ils_luminance_workspace_bytes(1080, 1920) <= L.ils_workspace_bytes(1080, 1920, 3, 1)
+
+
+def test_iterate_from_c_rejects_null_plan(L):
+    assert L.ils_iterate_from_c(None, None, None, 8, 8, 1, 1.0, 0.8, 1e-4, 201.0, 4, None) == -1

@@ -140,3 +140,29 @@ def test_energy_welsch_matches_oracle(torch, ils):
         es.append(e_gpu)
     assert all(b <= a * (1 + 1e-7) for a, b in zip(es, es[1:])), es
     plan.close()
+
+
+def test_explicit_c_parity_and_convergence_order(torch, ils):
+    """N iterations with c = 2 c0 and 4 c0 against the oracle; at a fixed N
+    the energy is lower for smaller c (Sec. 3.3.3); c < c0 is rejected."""
+    H, W, C = 128, 160, 1
+    lam, p, eps, N = 1.0, 0.8, 1e-4, 4
+    f = voronoi_image(H, W, C, 20, 0.05, seed=21)
+    ft = torch.from_numpy(f).cuda()
+    c0 = O.charbonnier_c0(p, eps)
+    plan = ils.Plan(H, W, C)
+    energies = []
+    for mult in (1.0, 2.0, 4.0):
+        u = plan.iterate_from(ft, ft, lam, p, eps, N, c=mult * c0)
+        torch.cuda.synchronize()
+        ref = O.ils(f[0].astype(np.float64), lam, p, eps, N, c=mult * c0)
+        mx, rel = _errs(u.cpu().numpy()[0], ref)
+        assert mx <= MAX_ABS and rel <= REL_L2, (mult, mx, rel)
+        energies.append(float(plan.energy(ft, u, lam, p, eps).cpu()))
+    assert energies[0] < energies[1] < energies[2], energies
+    u1 = plan.iterate_from(ft, ft, lam, p, eps, N, c=c0).cpu().numpy()
+    u2 = plan.smooth(ft, lam, p, eps, N).cpu().numpy()
+    assert np.array_equal(u1, u2)  # c = c0 is the default path bit for bit
+    with pytest.raises(Exception):
+        plan.iterate_from(ft, ft, lam, p, eps, N, c=0.9 * c0)
+    plan.close()
