@@ -56,6 +56,20 @@ __device__ __forceinline__ float mu_pen(float g, float a, float b, float l2r) {
     return mu_ns(g, a, b, l2r);
 }
 
+// Cross-lane moves inside a wavefront (no LDS allocation): the value of the
+// previous lane (a DPP wave shift), and the value of the last lane of a
+// T-lane slot broadcast to the whole slot (ds_swizzle bit mode, within
+// 32-lane groups; T a power of two <= 32).
+__device__ __forceinline__ float from_prev_lane(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138 /* wave_shr:1 */, 0xf, 0xf, false));
+}
+template <int T>
+__device__ __forceinline__ float from_slot_last_lane(float v) {
+  static_assert(T <= 32 && (T & (T - 1)) == 0, "slot must be a power of two within 32 lanes");
+  constexpr int pattern = (31 & ~(T - 1)) | ((T - 1) << 5);  // and-mask, or-mask, xor-mask 0
+  return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), pattern));
+}
+
 // Synchronisation inside one row slot.  When a slot lies within one
 // wavefront (T divides 64) its LDS exchange needs no workgroup barrier: the
 // LDS operations of a wavefront are performed in program order, so it is
@@ -324,16 +338,29 @@ __device__ __forceinline__ void row_body(const FrameDesc& d, int band, int ch, f
     const float2* ud = reinterpret_cast<const float2*>(sl + SLOT_F);
     const float a_exp = d.a_exp, inv_eps = d.inv_eps, kappa = d.kappa, l2r = d.log2_r;
     if (slot >= 1) {
+      // mu_x left of pair j equals mu_x right of pair j - 1.  When a slot is
+      // Q lanes of one wavefront, pair j - 1 sits in the previous lane (same
+      // n1) or, for lane 0, in lane Q - 1 at n1 - 1: take it from there.
+      constexpr bool kLaneReuse = (T == Q) && (T <= 32) && ((T & (T - 1)) == 0);
+      float mx1_prev = 0.0f;
       static_for<P>([&](auto n1c) {
         constexpr int n1 = decltype(n1c)::value;
         const int j = Q * n1 + t;
-        const int jm = (j == 0) ? M - 1 : j - 1;
         const int jp = (j == M - 1) ? 0 : j + 1;
-        const float2 c = uc[j], dn = ud[j], l = uc[jm], rr = uc[jp];
+        const float2 c = uc[j], dn = ud[j], rr = uc[jp];
         myd[n1] = make_float2(mu_pen<PEN>(dn.x - c.x, a_exp, inv_eps, l2r), mu_pen<PEN>(dn.y - c.y, a_exp, inv_eps, l2r));
-        const float mxl = mu_pen<PEN>(c.x - l.y, a_exp, inv_eps, l2r);
         const float mx0 = mu_pen<PEN>(c.y - c.x, a_exp, inv_eps, l2r);
         const float mx1 = mu_pen<PEN>(rr.x - c.y, a_exp, inv_eps, l2r);
+        float mxl;
+        if constexpr (kLaneReuse && n1 > 0) {
+          const float sh = from_prev_lane(mx1);
+          const float wr = from_slot_last_lane<T>(mx1_prev);
+          mxl = (t == 0) ? wr : sh;
+        } else {
+          const int jm = (j == 0) ? M - 1 : j - 1;
+          mxl = mu_pen<PEN>(c.x - uc[jm].y, a_exp, inv_eps, l2r);
+        }
+        mx1_prev = mx1;
         r[n1] = {fmaf(kappa, (mxl - mx0) - myd[n1].x, fv[n1].x), fmaf(kappa, (mx0 - mx1) - myd[n1].y, fv[n1].y)};
         // batches of five positions: their LDS reads issue together, while
         // the registers of later positions are not claimed early

@@ -108,6 +108,8 @@ def test_energy_along_iterations_matches_oracle(torch, ils):
     iterates; and the decrease the majorise-minimise argument guarantees."""
     H, W, C = 256, 256, 3
     lam, p, eps = 1.0, 0.8, 1e-4
+    # the library receives float32 parameters: the oracle energy uses the same values
+    p32, eps32 = float(np.float32(p)), float(np.float32(eps))
     f = voronoi_image(H, W, C, 40, 0.05, seed=0)
     ft = torch.from_numpy(f).cuda()
     plan = ils.Plan(H, W, C)
@@ -116,7 +118,7 @@ def test_energy_along_iterations_matches_oracle(torch, ils):
     for n in range(7):
         e_gpu = float(plan.energy(ft, u, lam, p, eps).cpu())
         un = u.cpu().numpy().astype(np.float64)
-        e_ref = sum(O.energy(un[c], f[c], lam, p, eps) for c in range(C))
+        e_ref = sum(O.energy(un[c], f[c], lam, p32, eps32) for c in range(C))
         assert abs(e_gpu - e_ref) <= 1e-9 * e_ref, (n, e_gpu, e_ref)
         es.append(e_gpu)
         u = plan.iterate_from(ft, u, lam, p, eps, 1)
@@ -127,6 +129,7 @@ def test_energy_along_iterations_matches_oracle(torch, ils):
 def test_energy_welsch_matches_oracle(torch, ils):
     H, W, C = 90, 120, 3
     lam, gam = 20.0, 10 / 255
+    gam32 = float(np.float32(gam))
     f = clipart_image(H, W, C, K=8, seed=12)
     ft = torch.from_numpy(f).cuda()
     plan = ils.Plan(H, W, C)
@@ -135,7 +138,7 @@ def test_energy_welsch_matches_oracle(torch, ils):
         u = plan.smooth_welsch(ft, lam, gam, N)
         e_gpu = float(plan.energy(ft, u, lam, gamma=gam).cpu())
         un = u.cpu().numpy().astype(np.float64)
-        e_ref = sum(O.energy_welsch(un[c], f[c], lam, gam) for c in range(C))
+        e_ref = sum(O.energy_welsch(un[c], f[c], lam, gam32) for c in range(C))
         assert abs(e_gpu - e_ref) <= 1e-9 * e_ref, (N, e_gpu, e_ref)
         es.append(e_gpu)
     assert all(b <= a * (1 + 1e-7) for a, b in zip(es, es[1:])), es
