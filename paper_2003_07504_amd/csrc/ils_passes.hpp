@@ -276,6 +276,8 @@ __device__ __forceinline__ void row_body(const FrameDesc& d, int band, int ch, f
   for (int i = tid; i < M; i += blockDim.x) tws[i] = d.tw_row[i];
 
   float2 fv[P];
+  // u^0 = f (Algorithm 1): the data term is the slot's own u row in LDS
+  const bool f_is_u0 = (MODE == ROW_FIRST) && (d.f == d.u0);
   if constexpr (MODE == ROW_FIRST) {
     if (in_slot && lane < Q) {  // u^0 row of this slot, all loads in flight together
       const float2* urow = reinterpret_cast<const float2*>(d.u0 + (size_t)ch * H * W + (size_t)yrow * W);
@@ -284,7 +286,7 @@ __device__ __forceinline__ void row_body(const FrameDesc& d, int band, int ch, f
         constexpr int n1 = decltype(n1c)::value;
         uv[n1] = urow[Q * n1 + lane];
       });
-      if (out_slot) {
+      if (out_slot && !f_is_u0) {
         static_for<P>([&](auto n1c) {
           constexpr int n1 = decltype(n1c)::value;
           fv[n1] = frow[Q * n1 + lane];
@@ -348,6 +350,7 @@ __device__ __forceinline__ void row_body(const FrameDesc& d, int band, int ch, f
         const int j = Q * n1 + t;
         const int jp = (j == M - 1) ? 0 : j + 1;
         const float2 c = uc[j], dn = ud[j], rr = uc[jp];
+        if (f_is_u0) fv[n1] = c;
         myd[n1] = make_float2(mu_pen<PEN>(dn.x - c.x, a_exp, inv_eps, l2r), mu_pen<PEN>(dn.y - c.y, a_exp, inv_eps, l2r));
         const float mx0 = mu_pen<PEN>(c.y - c.x, a_exp, inv_eps, l2r);
         const float mx1 = mu_pen<PEN>(rr.x - c.y, a_exp, inv_eps, l2r);

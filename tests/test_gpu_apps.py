@@ -148,7 +148,7 @@ def test_energy_welsch_matches_oracle(torch, ils):
 def test_explicit_c_parity_and_convergence_order(torch, ils):
     """N iterations with c = 2 c0 and 4 c0 against the oracle; at a fixed N
     the energy is lower for smaller c (Sec. 3.3.3); c < c0 is rejected."""
-    H, W, C = 128, 160, 1
+    H, W, C = 120, 256, 1
     lam, p, eps, N = 1.0, 0.8, 1e-4, 4
     f = voronoi_image(H, W, C, 20, 0.05, seed=21)
     ft = torch.from_numpy(f).cuda()
