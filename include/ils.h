@@ -172,7 +172,8 @@ int ils_iterate_from(ils_plan* plan, const float* f, const float* u0, int H, int
 /* As ils_iterate_from with the constant c of Eq. (5) given explicitly
  * instead of c = c0 = p eps^(p/2 - 1) (Sec. 3.3.3: any c >= c0 keeps the
  * energy decreasing; smaller c converges faster).  c < c0 (beyond a relative
- * 1e-6) is ILS_ERR_INVALID_ARG.  For convergence studies. */
+ * 1e-6) is ILS_ERR_INVALID_ARG; c within a relative 1e-6 of c0 runs the
+ * default c = c0 path exactly.  For convergence studies. */
 int ils_iterate_from_c(ils_plan* plan, const float* f, const float* u0, int H, int W, int C, float lambda,
                        float p, float eps, float c, int N, float* out);
 

@@ -672,8 +672,11 @@ int ils_iterate_from_c(ils_plan* plan, const float* f, const float* u0, int H, i
   }
   FrameDesc d;
   fill_desc(plan, d, H, W, C, lambda, p, eps);
-  d.kappa = (float)((double)lambda * (double)c / 2.0);
-  d.log2_r = (float)std::log2(c0 / (double)c);
+  // c within float rounding of c0 is c0 itself (the default path, bit for bit)
+  if (std::fabs((double)c - c0) > 1e-6 * c0) {
+    d.kappa = (float)((double)lambda * (double)c / 2.0);
+    d.log2_r = (float)std::log2(c0 / (double)c);
+  }
   d.f = f;
   d.u0 = u0;
   d.out = out;

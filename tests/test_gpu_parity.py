@@ -385,3 +385,27 @@ def test_tile_shapes_are_bitwise_equal(torch, ils, H, W, C):
     with pytest.raises(Exception):
         fresh.set_shapes(H, W, C, nr, 0)
     fresh.close()
+
+
+def test_tune_cache_file_is_read_and_written(torch, ils, tmp_path, monkeypatch):
+    """ILS_TUNE_CACHE: a stored choice (rows per band, columns per tile) is
+    taken without timing; a newly tuned size is appended."""
+    cache = tmp_path / "tune.txt"
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    nr, nc = ils.shape_variants(720, 1280)
+    assert nr > 1 and nc > 1
+    # find the band height / tile width of shape index 1 by forcing it on a plan
+    cache.write_text(f"{arch} 720 1280 1 0 0\n")  # no such shape: ignored
+    monkeypatch.setenv("ILS_TUNE_CACHE", str(cache))
+    plan = ils.Plan(720, 1280, 1)
+    r, c = plan.tune(720, 1280, 1)  # tuned now (the stored line named no compiled shape)
+    plan.close()
+    lines = cache.read_text().split("\n")
+    last = [ln for ln in lines if ln.strip()][-1].split()
+    assert last[:4] == [arch, "720", "1280", "1"]
+    g, s = int(last[4]), int(last[5])
+    assert g > 0 and s > 0
+    # a fresh plan reads the appended line and returns the same shapes untimed
+    plan = ils.Plan(720, 1280, 1)
+    assert plan.tune(720, 1280, 1) == (r, c)
+    plan.close()
