@@ -69,7 +69,7 @@ constexpr int kMaxBatchFrames = 4096;
 
 // Per-length device tables (offsets into the plan's table buffer).
 struct LenTables {
-  size_t tw, tw2, sx, sy;  // byte offsets
+  size_t tw, tw2, sx, sy, twm;  // byte offsets
 };
 
 // Pinned host staging for the small host-to-device uploads (batch work
@@ -207,6 +207,7 @@ static void fill_desc(const ils_plan* plan, FrameDesc& d, int H, int W, int C, f
   const LenTables& tc = plan->tab.at(H);
   d.tw_row = reinterpret_cast<const cf*>(plan->tables + tr.tw);
   d.tw2_row = reinterpret_cast<const cf*>(plan->tables + tr.tw2);
+  d.twm_row = reinterpret_cast<const cf*>(plan->tables + tr.twm);
   d.sx = reinterpret_cast<const float*>(plan->tables + tr.sx);
   d.tw_col = reinterpret_cast<const cf*>(plan->tables + tc.tw);
   d.sy = reinterpret_cast<const float*>(plan->tables + tc.sy);
@@ -527,6 +528,15 @@ int ils_plan_create(ils_plan** plan_out, int max_H, int max_W, int max_C, int ma
       double s = std::sin(M_PI * (double)l / (double)L);
       sy[l] = (float)(4.0 * s * s);
     }
+    // the row transforms' twiddles as a P x (Q|1) matrix, entry [k1][t] =
+    // exp(-2 pi i t k1 / L): lanes that walk either index hit distinct banks
+    const LenOps* o = kOps[i]();
+    const int P = o->P, Q = o->Q, QP = Q | 1;
+    t.twm = put(sizeof(cf) * P * QP);
+    cf* twm = reinterpret_cast<cf*>(host.data() + t.twm);
+    tw = reinterpret_cast<cf*>(host.data() + t.tw);
+    for (int k1 = 0; k1 < P; ++k1)
+      for (int q = 0; q < QP; ++q) twm[k1 * QP + q] = q < Q ? tw[q * k1] : cf{0.0f, 0.0f};
     plan->tab[L] = t;
   }
   hipError_t e = hipMalloc(&plan->tables, host.size());

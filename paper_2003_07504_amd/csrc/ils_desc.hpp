@@ -21,6 +21,7 @@ struct FrameDesc {
   cf* specB;
   const cf* tw_row;   // exp(-2 pi i j / M), j < M          (M = W/2)
   const cf* tw2_row;  // exp(-pi i k / M),  k <= M
+  const cf* twm_row;  // exp(-2 pi i t k1 / M) at [k1 * (Q|1) + t], M = P Q
   const float* sx;    // 4 sin^2(pi k / W), k <= M
   const cf* tw_col;   // exp(-2 pi i j / H), j < H
   const float* sy;    // 4 sin^2(pi l / H), l < H

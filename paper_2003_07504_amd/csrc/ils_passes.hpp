@@ -91,7 +91,7 @@ struct RowGeom {
   static constexpr int T = P > Q ? P : Q;    // lanes per row slot
   static constexpr int QP = Q | 1;           // padded exchange row (odd => conflict-free)
   static constexpr int SLOT_F = 2 * P * QP;  // floats of LDS per row slot (>= W)
-  static constexpr int TAB_F = 2 * M;        // twiddle table exp(-2 pi i j / M), j < M
+  static constexpr int TAB_F = 2 * P * QP;   // twiddles exp(-2 pi i t k1 / M) at [k1][t]
   static constexpr int NPOST = (M + 1 + T - 1) / T;  // post-process elements per lane
 };
 
@@ -197,9 +197,10 @@ template <int P, int Q>
 __device__ __forceinline__ void c2r_exchange(const cf (&v)[Q], int k1, const cf* tws, cf* slc) {
   constexpr int QP = Q | 1;
   cf w[Q];
+  const cf* wrow = tws + k1 * QP;
   static_for<Q>([&](auto tc) {
     constexpr int t = decltype(tc)::value;
-    if constexpr (t > 0) w[t] = tws[t * k1];
+    if constexpr (t > 0) w[t] = wrow[t];
   });
   static_for<Q>([&](auto tc) {
     constexpr int t = decltype(tc)::value;
@@ -273,7 +274,7 @@ __device__ __forceinline__ void row_body(const FrameDesc& d, int band, int ch, f
   // per-lane factors of the real-FFT twiddles (one load each, issued first)
   const cf w2lane = d.tw2_row[lane];  // exp(-i pi lane / M)
   // twiddle table -> LDS
-  for (int i = tid; i < M; i += blockDim.x) tws[i] = d.tw_row[i];
+  for (int i = tid; i < P * Geo::QP; i += blockDim.x) tws[i] = d.twm_row[i];
 
   float2 fv[P];
   // u^0 = f (Algorithm 1): the data term is the slot's own u row in LDS
@@ -399,7 +400,7 @@ __device__ __forceinline__ void row_body(const FrameDesc& d, int band, int ch, f
     dft<P, -1>(r);
     static_for<P>([&](auto k1c) {
       constexpr int k1 = decltype(k1c)::value;
-      if (k1 != 0) r[k1] = cmul(r[k1], tws[t * k1]);
+      if (k1 != 0) r[k1] = cmul(r[k1], tws[k1 * QP + t]);
     });
   }
   __syncthreads();
@@ -452,7 +453,7 @@ __device__ __forceinline__ void row_final_body(const FrameDesc& d, int band, int
   const bool in_slot = slot < Gv;
   const int yrow = in_slot ? y0 + slot : 0;
   const cf w2lane = d.tw2_row[lane];
-  for (int i = tid; i < M; i += blockDim.x) tws[i] = d.tw_row[i];
+  for (int i = tid; i < P * Geo::QP; i += blockDim.x) tws[i] = d.twm_row[i];
   cf v[Q];
   if (in_slot && lane < P) {
     const cf* X = d.specB + (size_t)ch * H * ldS + (size_t)yrow * ldS;
