@@ -210,6 +210,7 @@ static void fill_desc(const ils_plan* plan, FrameDesc& d, int H, int W, int C, f
   d.twm_row = reinterpret_cast<const cf*>(plan->tables + tr.twm);
   d.sx = reinterpret_cast<const float*>(plan->tables + tr.sx);
   d.tw_col = reinterpret_cast<const cf*>(plan->tables + tc.tw);
+  d.twm_col = reinterpret_cast<const cf*>(plan->tables + tc.twm);
   d.sy = reinterpret_cast<const float*>(plan->tables + tc.sy);
   d.H = H;
   d.W = W;

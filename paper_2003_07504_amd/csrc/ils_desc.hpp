@@ -24,6 +24,7 @@ struct FrameDesc {
   const cf* twm_row;  // exp(-2 pi i t k1 / M) at [k1 * (Q|1) + t], M = P Q
   const float* sx;    // 4 sin^2(pi k / W), k <= M
   const cf* tw_col;   // exp(-2 pi i j / H), j < H
+  const cf* twm_col;  // exp(-2 pi i j k1 / H) at [k1 * (Q|1) + j], H = P Q
   const float* sy;    // 4 sin^2(pi l / H), l < H
   int H, W, C, ldS;
   float kappa;      // lambda * c / 2, c >= c0 = p eps^(p/2 - 1) (Welsch: c = 2)

@@ -133,9 +133,16 @@ template <int P, int Q, int S>
 struct ColGeom {
   static constexpr int H = P * Q;
   static constexpr int T = P > Q ? P : Q;
-  static constexpr int TAB_F = 2 * H;  // twiddles exp(-2 pi i j / H)
+  static constexpr int QT = Q | 1;  // row stride of the twiddle matrix
+  // Tables: the twiddles as a P x QT matrix [k1][j] plus Sy[l] = 4 sin^2(pi l / H)
+  // when they fit beside the exchange, else the twiddles exp(-2 pi i l / H)
+  // as a vector (indices multiplied out, Sy formed from them).
+  static constexpr int TAB_MAT_F = 2 * P * QT + H;
+  static constexpr int TAB_VEC_F = 2 * H;
   static constexpr int KS = (S >= 16) ? Q * S : Q * S + ((S - (Q * S) % 16) + 16) % 16;
   static constexpr int EX_F = 2 * P * KS;
+  static constexpr bool MAT = 4 * (EX_F + TAB_MAT_F) <= 163840;
+  static constexpr int TAB_F = MAT ? TAB_MAT_F : TAB_VEC_F;
   static constexpr int LDS_F = EX_F + TAB_F;
   static constexpr bool fits = 4 * LDS_F <= 163840 && S * T <= 1024;
 };
@@ -493,7 +500,7 @@ __device__ __forceinline__ void row_final_body(const FrameDesc& d, int band, int
 template <int P, int Q, int S_>
 __device__ __forceinline__ void col_body(const FrameDesc& d, int tile, int ch, float* smem) {
   using Geo = ColGeom<P, Q, S_>;
-  constexpr int H = Geo::H, S = S_, KS = Geo::KS;
+  constexpr int H = Geo::H, S = S_, KS = Geo::KS, QT = Geo::QT;
   const int ldS = d.ldS;
   const int Wh = d.W / 2 + 1;
   const int tid = threadIdx.x;
@@ -505,7 +512,8 @@ __device__ __forceinline__ void col_body(const FrameDesc& d, int tile, int ch, f
   const cf* in = d.specA + (size_t)ch * H * ldS + cc;
   cf* out = d.specB + (size_t)ch * H * ldS + cc;
   cf* ex = reinterpret_cast<cf*>(smem);
-  cf* tws = reinterpret_cast<cf*>(smem + Geo::EX_F);
+  cf* tws = reinterpret_cast<cf*>(smem + Geo::EX_F);  // matrix [k1][j] (row stride QT) or vector [l]
+  float* syl = smem + Geo::EX_F + 2 * P * QT;          // Sy[l] (matrix layout only)
 
   cf x[P];
   if (j < Q) {  // stage A loads first: lane n2 = j, rows Q n1 + n2
@@ -515,13 +523,18 @@ __device__ __forceinline__ void col_body(const FrameDesc& d, int tile, int ch, f
     });
   }
   const float sxk = d.sx[cc];
-  for (int i = tid; i < H; i += blockDim.x) tws[i] = d.tw_col[i];
+  if constexpr (Geo::MAT) {
+    for (int i = tid; i < P * QT; i += blockDim.x) tws[i] = d.twm_col[i];
+    for (int i = tid; i < H; i += blockDim.x) syl[i] = d.sy[i];
+  } else {
+    for (int i = tid; i < H; i += blockDim.x) tws[i] = d.tw_col[i];
+  }
   __syncthreads();
   if (j < Q) {
     cf w[P];
     static_for<P>([&](auto k1c) {
       constexpr int k1 = decltype(k1c)::value;
-      if constexpr (k1 > 0) w[k1] = tws[j * k1];
+      if constexpr (k1 > 0) w[k1] = Geo::MAT ? tws[k1 * QT + j] : tws[j * k1];
     });
     dft<P, -1>(x);
     static_for<P>([&](auto k1c) {
@@ -541,15 +554,21 @@ __device__ __forceinline__ void col_body(const FrameDesc& d, int tile, int ch, f
     const float ksx = fmaf(kappa, sxk, 1.0f);
     static_for<Q>([&](auto k2c) {
       constexpr int k2 = decltype(k2c)::value;
-      const cf w = tws[j + P * k2];
-      const float omc = 1.0f - w.x;
-      const float den = fmaf(kappa, fmaf(omc, omc, w.y * w.y), ksx);
+      float sy;
+      if constexpr (Geo::MAT) {
+        sy = syl[j + P * k2];
+      } else {
+        const cf w = tws[j + P * k2];
+        const float omc = 1.0f - w.x;
+        sy = fmaf(omc, omc, w.y * w.y);
+      }
+      const float den = fmaf(kappa, sy, ksx);
       y[k2] = cscale(y[k2], scale * __builtin_amdgcn_rcpf(den));
     });
     dft<Q, +1>(y);
     static_for<Q>([&](auto n2c) {
       constexpr int n2 = decltype(n2c)::value;
-      ex[j * KS + n2 * S + s] = (n2 == 0) ? y[n2] : cmulc(y[n2], tws[n2 * j]);  // slots this lane read
+      ex[j * KS + n2 * S + s] = (n2 == 0) ? y[n2] : cmulc(y[n2], Geo::MAT ? tws[j * QT + n2] : tws[n2 * j]);
     });
   }
   __syncthreads();
