@@ -129,22 +129,38 @@ constexpr int row_band_alt() {
 
 // Column tile of S spectrum columns.  The exchange row of one k1 is padded
 // so that successive k1 groups land on different LDS banks.
+constexpr int col_ks(int Q, int S) { return (S >= 16) ? Q * S : Q * S + ((S - (Q * S) % 16) + 16) % 16; }
+constexpr int col_ex_f(int P, int Q, int S) { return 2 * P * col_ks(Q, S); }
+constexpr bool col_fits(int P, int Q, int S, int tab_f) {
+  return 4 * (col_ex_f(P, Q, S) + tab_f) <= 163840 && S * (P > Q ? P : Q) <= 1024;
+}
+
+// Tables of a column length: the twiddles as a P x (Q|1) matrix [k1][j] plus
+// Sy[l] = 4 sin^2(pi l / H) when they fit beside the exchange of the widest
+// tile the plain vector of twiddles allows, else that vector (indices
+// multiplied out, Sy formed from the twiddles).  The choice is per length, so
+// every tile width of a length computes the same bits.
+template <int P, int Q>
+struct ColTables {
+  static constexpr int H = P * Q;
+  static constexpr int MAT_F = 2 * P * (Q | 1) + H;
+  static constexpr int VEC_F = 2 * H;
+  static constexpr int WIDEST = col_fits(P, Q, 16, VEC_F) ? 16 : col_fits(P, Q, 8, VEC_F) ? 8 : 4;
+  static constexpr bool MAT = col_fits(P, Q, WIDEST, MAT_F);
+  static constexpr int TAB_F = MAT ? MAT_F : VEC_F;
+};
+
 template <int P, int Q, int S>
 struct ColGeom {
   static constexpr int H = P * Q;
   static constexpr int T = P > Q ? P : Q;
   static constexpr int QT = Q | 1;  // row stride of the twiddle matrix
-  // Tables: the twiddles as a P x QT matrix [k1][j] plus Sy[l] = 4 sin^2(pi l / H)
-  // when they fit beside the exchange, else the twiddles exp(-2 pi i l / H)
-  // as a vector (indices multiplied out, Sy formed from them).
-  static constexpr int TAB_MAT_F = 2 * P * QT + H;
-  static constexpr int TAB_VEC_F = 2 * H;
-  static constexpr int KS = (S >= 16) ? Q * S : Q * S + ((S - (Q * S) % 16) + 16) % 16;
-  static constexpr int EX_F = 2 * P * KS;
-  static constexpr bool MAT = 4 * (EX_F + TAB_MAT_F) <= 163840;
-  static constexpr int TAB_F = MAT ? TAB_MAT_F : TAB_VEC_F;
+  static constexpr int KS = col_ks(Q, S);
+  static constexpr int EX_F = col_ex_f(P, Q, S);
+  static constexpr bool MAT = ColTables<P, Q>::MAT;
+  static constexpr int TAB_F = ColTables<P, Q>::TAB_F;
   static constexpr int LDS_F = EX_F + TAB_F;
-  static constexpr bool fits = 4 * LDS_F <= 163840 && S * T <= 1024;
+  static constexpr bool fits = col_fits(P, Q, S, TAB_F);
 };
 
 // Default column tile: the widest whose exchange and table fit the 160 KB of
