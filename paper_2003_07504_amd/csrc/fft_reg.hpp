@@ -2,12 +2,15 @@
 //
 // dft<N, DIR>(x) transforms N complex values held in registers, natural
 // order in and natural order out:  X[k] = sum_n x[n] exp(DIR * 2 pi i n k / N)
-// (DIR = -1 forward, +1 inverse, unnormalised).  Composite N is split as
-// N = R * L (R = 4, 2, 3 or 5): L interleaved R-point DFTs, a twiddle by
-// exp(DIR 2 pi i n2 k1 / N), then R L-point DFTs.  Every index and every
-// twiddle is a compile-time constant, so after inlining the whole transform
-// is straight-line register code; twiddle constants are evaluated in double
-// precision at compile time and rounded once to float.
+// (DIR = -1 forward, +1 inverse, unnormalised).  A length with two or more
+// distinct prime factors is split N = N1 * N2 with coprime factors by the
+// prime-factor (Good-Thomas) mapping, which needs no twiddle factors; a prime
+// power is split N = R * L (R = 4, 2, 3 or 5) Cooley-Tukey style: L
+// interleaved R-point DFTs, a twiddle by exp(DIR 2 pi i n2 k1 / N), then R
+// L-point DFTs.  Every index and every twiddle is a compile-time constant, so
+// after inlining the whole transform is straight-line register code; twiddle
+// constants are evaluated in double precision at compile time and rounded
+// once to float.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -161,6 +164,58 @@ constexpr bool is_235_smooth(int n) {
   return n == 1;
 }
 
+// Prime-factor split of n: the prime-power part of n for its largest prime
+// (N1), if n has another prime factor too; 0 when n is a prime power.
+constexpr int pfa_split(int n) {
+  int part = 1;
+  for (int p : {2, 3, 5}) {
+    int q = 1;
+    while (n % (q * p) == 0) q *= p;
+    if (q > 1) part = q;
+  }
+  return (part > 1 && part < n) ? part : 0;
+}
+
+constexpr int inverse_mod(int a, int m) {
+  for (int x = 1; x < m; ++x)
+    if ((a * x) % m == 1) return x;
+  return 1;
+}
+
+template <int N, int DIR>
+__host__ __device__ __forceinline__ void dft(cf (&x)[N]);
+
+// Good-Thomas: input n = (N2 n1 + N1 n2) mod N, output k = (N2 t2 k1 + N1 t1 k2)
+// mod N with t2 = N2^-1 mod N1, t1 = N1^-1 mod N2; then exp(2 pi i n k / N)
+// factors into exp(2 pi i n1 k1 / N1) exp(2 pi i n2 k2 / N2).
+template <int N1, int N2, int DIR>
+__host__ __device__ __forceinline__ void dft_pfa(cf (&x)[N1 * N2]) {
+  constexpr int N = N1 * N2;
+  constexpr int t2 = inverse_mod(N2 % N1, N1), t1 = inverse_mod(N1 % N2, N2);
+  cf a[N1][N2];
+  static_for<N2>([&](auto n2c) {
+    constexpr int n2 = decltype(n2c)::value;
+    cf t[N1];
+    static_for<N1>([&](auto n1c) {
+      constexpr int n1 = decltype(n1c)::value;
+      t[n1] = x[(N2 * n1 + N1 * n2) % N];
+    });
+    dft<N1, DIR>(t);
+    static_for<N1>([&](auto k1c) {
+      constexpr int k1 = decltype(k1c)::value;
+      a[k1][n2] = t[k1];
+    });
+  });
+  static_for<N1>([&](auto k1c) {
+    constexpr int k1 = decltype(k1c)::value;
+    dft<N2, DIR>(a[k1]);
+    static_for<N2>([&](auto k2c) {
+      constexpr int k2 = decltype(k2c)::value;
+      x[(N2 * t2 * k1 + N1 * t1 * k2) % N] = a[k1][k2];
+    });
+  });
+}
+
 template <int N, int DIR>
 __host__ __device__ __forceinline__ void dft(cf (&x)[N]) {
   static_assert(is_235_smooth(N), "register DFT length must be 2/3/5-smooth");
@@ -173,6 +228,8 @@ __host__ __device__ __forceinline__ void dft(cf (&x)[N]) {
     dft4<DIR>(x[0], x[1], x[2], x[3]);
   } else if constexpr (N == 5) {
     dft5<DIR>(x[0], x[1], x[2], x[3], x[4]);
+  } else if constexpr (pfa_split(N) != 0) {
+    dft_pfa<pfa_split(N), N / pfa_split(N), DIR>(x);
   } else {
     constexpr int R = pick_radix(N);
     constexpr int L = N / R;
