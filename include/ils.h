@@ -150,6 +150,17 @@ size_t ils_luminance_workspace_bytes(int max_H, int max_W);
 int ils_smooth_luminance(ils_plan* plan, const float* f, int H, int W, float lambda, float p, float eps,
                          int N, float k, float* out);
 
+/* Single-scale HDR tone mapping (Sec. 4, the application shown with p = 1,
+ * lambda = 10): on a planar linear-radiance RGB frame f (3 x H x W, > 0),
+ * L = log max(Y, 1e-6) with Y = 0.299 R + 0.587 G + 0.114 B; base B = u^N of
+ * Algorithm 1 on L; detail D = L - B; L' = (B - max B) s + detail * D with
+ * s = log(contrast) / (max B - min B) (s = 1 for a flat base); out_c =
+ * f_c exp(L' - L), which keeps the colour ratios of every pixel.  The output
+ * is linear (no display gamma) and not clipped.  contrast > 1, detail >= 0
+ * finite.  Workspace as ils_smooth_luminance.  out == f allowed. */
+int ils_tone_map(ils_plan* plan, const float* f, int H, int W, float lambda, float p, float eps, int N,
+                 float contrast, float detail, float* out);
+
 /* Energy of Eq. (1), E(u) = sum (u - f)^2 + lambda sum (phi(D_x u) +
  * phi(D_y u)) over all pixels and channels, periodic differences, computed
  * in double: phi = (x^2 + eps)^(p/2) (Eq. (2)) for ils_energy, the Welsch

@@ -48,7 +48,7 @@ __all__ = [
     "transfer_functions", "fft_solve", "ils", "ils_channels", "energy",
     "dense_ls_step", "fixed_point_residual", "phi_welsch", "dphi_welsch",
     "welsch_c0", "mu_update_welsch", "ils_welsch", "energy_welsch",
-    "luma", "ils_luminance", "detail_enhance",
+    "luma", "ils_luminance", "detail_enhance", "tone_map",
 ]
 
 
@@ -335,3 +335,25 @@ def ils_luminance(f, lam, p, eps=1e-4, N=4, k=0.0, workers=None):
     y = luma(f)
     v = detail_enhance(y, ils(y, lam, p, eps, N, workers=workers), k)
     return f + (v - y)[None]
+
+
+LUMA_FLOOR = 1e-6  # luminance below this is taken as this before the logarithm
+
+
+def tone_map(f, lam, p, eps=1e-4, N=4, contrast=100.0, detail=1.0, workers=None):
+    """Single-scale HDR tone mapping on the logarithm of the luminance (the
+    application the paper shows with p = 1, lambda = 10): L = log Y, base
+    B = ILS(L), detail D = L - B; the base is scaled so that its range is
+    log(contrast) and its maximum is 0, the detail is kept (times `detail`);
+    each channel is multiplied by the ratio of new to old luminance, which
+    keeps the colour ratios of every pixel."""
+    f = np.asarray(f, dtype=np.float64)
+    if f.ndim != 3 or f.shape[0] != 3:
+        raise ValueError("tone_map expects a (3, H, W) RGB frame")
+    y = np.maximum(luma(f), LUMA_FLOOR)
+    L = np.log(y)
+    B = ils(L, lam, p, eps, N, workers=workers)
+    bmax, bmin = float(B.max()), float(B.min())
+    s = np.log(contrast) / (bmax - bmin) if bmax > bmin else 1.0
+    Lout = (B - bmax) * s + detail * (L - B)
+    return f * (np.exp(Lout) / y)[None]

@@ -260,6 +260,11 @@ hipError_t ilsk_launch_luma(const float* rgb, float* y, long long plane, hipStre
 hipError_t ilsk_launch_recombine(const float* f, const float* y, const float* v, float* out, long long plane,
                                  hipStream_t st);
 
+hipError_t ilsk_launch_loglum(const float* rgb, float* L, long long plane, float floor_y, hipStream_t st);
+hipError_t ilsk_launch_minmax(const float* B, long long plane, float* scratch, float* mm, hipStream_t st);
+hipError_t ilsk_launch_tonemap(const float* f, const float* L, const float* B, const float* mm, float log_contrast,
+                               float detail, float* out, long long plane, hipStream_t st);
+
 // ---------------------------------------------------------------- tuner
 // Lengths of 480 and more offer two row-band and two column-tile shapes.
 // The first call for an image size times each shape on the plan's stream
@@ -789,6 +794,44 @@ int ils_smooth_luminance(ils_plan* plan, const float* f, int H, int W, float lam
   rc = run_frame(plan, d, N);
   if (rc != ILS_OK) return rc;
   return record(plan, ilsk_launch_recombine(f, Y, V, out, plane, plan->stream));
+}
+
+int ils_tone_map(ils_plan* plan, const float* f, int H, int W, float lambda, float p, float eps, int N,
+                 float contrast, float detail, float* out) {
+  if (!plan || !f || !out || !finite_f(contrast) || !(contrast > 1.0f) || !finite_f(detail) || detail < 0.0f)
+    return ILS_ERR_INVALID_ARG;
+  int rc = check_params(lambda, p, eps, N);
+  if (rc != ILS_OK) return rc;
+  rc = check_size(plan, H, W, 1);
+  if (rc != ILS_OK) return rc;
+  if (plan->ws_bytes < ils_luminance_workspace_bytes(H, W)) return ILS_ERR_WORKSPACE;
+  const long long plane = (long long)H * W;
+  char* base = plan->ws + kBatchHeaderBytes;
+  const size_t spec = frame_ws_bytes(H, W, 1);
+  float* L = reinterpret_cast<float*>(base + spec);
+  float* B = reinterpret_cast<float*>(base + spec + align_up((size_t)plane * sizeof(float), 256));
+  float* scratch = reinterpret_cast<float*>(plan->ws);  // header: min/max partials, then the pair
+  float* mm = scratch + 2 * 256;
+  hipError_t e = ilsk_launch_loglum(f, L, plane, 1e-6f, plan->stream);
+  if (e != hipSuccess) return record(plan, e);
+  if (N == 0 || lambda == 0.0f) {
+    e = hipMemcpyAsync(B, L, (size_t)plane * sizeof(float), hipMemcpyDeviceToDevice, plan->stream);
+    if (e != hipSuccess) return record(plan, e);
+  } else {
+    FrameDesc d;
+    fill_desc(plan, d, H, W, 1, lambda, p, eps);
+    d.f = L;
+    d.u0 = L;
+    d.out = B;
+    d.specA = reinterpret_cast<cf*>(base);
+    d.specB = reinterpret_cast<cf*>(base + (size_t)H * d.ldS * sizeof(cf));
+    rc = run_frame(plan, d, N);
+    if (rc != ILS_OK) return rc;
+  }
+  e = ilsk_launch_minmax(B, plane, scratch, mm, plan->stream);
+  if (e == hipSuccess)
+    e = ilsk_launch_tonemap(f, L, B, mm, (float)std::log((double)contrast), detail, out, plane, plan->stream);
+  return record(plan, e);
 }
 
 int ils_smooth_batch(ils_plan* plan, const ils_frame* frames, int n) {

@@ -2,6 +2,7 @@
 //   * luminance-only colour mode: Y = 0.299 R + 0.587 G + 0.114 B, smooth Y,
 //     add the change of Y back to every channel (a YUV round trip with U, V
 //     unchanged);
+//   * single-scale HDR tone mapping on the logarithm of the luminance;
 //   * the energy of Eq. (1) for the Charbonnier (Eq. (2)) and Welsch
 //     (Eq. (18)) penalties, accumulated in double, for convergence studies.
 // Elementwise kernels are grid-stride loops over the pixels of a plane.
@@ -34,6 +35,78 @@ __global__ void __launch_bounds__(kThreads) k_recombine(const float* f, const fl
     out[i] = r + dlt;
     out[i + plane] = g + dlt;
     out[i + 2 * plane] = b + dlt;
+  }
+}
+
+// log of the luminance, floored (HDR tone mapping works on log Y)
+__global__ void __launch_bounds__(kThreads) k_loglum(const float* __restrict__ rgb, float* __restrict__ L,
+                                                      long long plane, float floor_y) {
+  const long long stride = (long long)gridDim.x * kThreads;
+  for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < plane; i += stride) {
+    const float y = fmaf(0.114f, rgb[i + 2 * plane], fmaf(0.587f, rgb[i + plane], 0.299f * rgb[i]));
+    L[i] = logf(fmaxf(y, floor_y));
+  }
+}
+
+// min and max of a plane: per-block partials, then one block
+constexpr int kMinMaxBlocks = 256;
+__global__ void __launch_bounds__(kThreads) k_minmax_partial(const float* __restrict__ b, long long plane,
+                                                              float* partial) {
+  float lo = INFINITY, hi = -INFINITY;
+  for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < plane; i += (long long)kMinMaxBlocks * kThreads) {
+    const float v = b[i];
+    lo = fminf(lo, v);
+    hi = fmaxf(hi, v);
+  }
+  __shared__ float rl[kThreads], rh[kThreads];
+  rl[threadIdx.x] = lo;
+  rh[threadIdx.x] = hi;
+  __syncthreads();
+  for (int s = kThreads / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      rl[threadIdx.x] = fminf(rl[threadIdx.x], rl[threadIdx.x + s]);
+      rh[threadIdx.x] = fmaxf(rh[threadIdx.x], rh[threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partial[2 * blockIdx.x] = rl[0];
+    partial[2 * blockIdx.x + 1] = rh[0];
+  }
+}
+
+__global__ void __launch_bounds__(kMinMaxBlocks) k_minmax_final(const float* partial, float* mm) {
+  __shared__ float rl[kMinMaxBlocks], rh[kMinMaxBlocks];
+  rl[threadIdx.x] = partial[2 * threadIdx.x];
+  rh[threadIdx.x] = partial[2 * threadIdx.x + 1];
+  __syncthreads();
+  for (int s = kMinMaxBlocks / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      rl[threadIdx.x] = fminf(rl[threadIdx.x], rl[threadIdx.x + s]);
+      rh[threadIdx.x] = fmaxf(rh[threadIdx.x], rh[threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    mm[0] = rl[0];
+    mm[1] = rh[0];
+  }
+}
+
+// out_c = f_c exp(L' - L), L' = (B - max B) s + detail (L - B), s = log(contrast) / (max B - min B)
+__global__ void __launch_bounds__(kThreads) k_tonemap(const float* f, const float* __restrict__ L,
+                                                       const float* __restrict__ B, const float* __restrict__ mm,
+                                                       float log_contrast, float detail, float* out, long long plane) {
+  const float bmin = mm[0], bmax = mm[1];
+  const float s = bmax > bmin ? log_contrast / (bmax - bmin) : 1.0f;
+  const long long stride = (long long)gridDim.x * kThreads;
+  for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < plane; i += stride) {
+    const float l = L[i], b = B[i];
+    const float g = expf(fmaf(b - bmax, s, detail * (l - b)) - l);
+    const float r = f[i], gg = f[i + plane], bb = f[i + 2 * plane];
+    out[i] = r * g;
+    out[i + plane] = gg * g;
+    out[i + 2 * plane] = bb * g;
   }
 }
 
@@ -109,6 +182,27 @@ hipError_t ilsk_launch_luma(const float* rgb, float* y, long long plane, hipStre
 hipError_t ilsk_launch_recombine(const float* f, const float* y, const float* v, float* out, long long plane,
                                  hipStream_t st) {
   hipLaunchKernelGGL(k_recombine, dim3(grid_for(plane)), dim3(kThreads), 0, st, f, y, v, out, plane);
+  return hipGetLastError();
+}
+
+hipError_t ilsk_launch_loglum(const float* rgb, float* L, long long plane, float floor_y, hipStream_t st) {
+  hipLaunchKernelGGL(k_loglum, dim3(grid_for(plane)), dim3(kThreads), 0, st, rgb, L, plane, floor_y);
+  return hipGetLastError();
+}
+
+// min/max of B into mm[0..1]; scratch holds 2 * 256 floats of partials
+hipError_t ilsk_launch_minmax(const float* B, long long plane, float* scratch, float* mm, hipStream_t st) {
+  hipLaunchKernelGGL(k_minmax_partial, dim3(kMinMaxBlocks), dim3(kThreads), 0, st, B, plane, scratch);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_minmax_final, dim3(1), dim3(kMinMaxBlocks), 0, st, scratch, mm);
+  return hipGetLastError();
+}
+
+hipError_t ilsk_launch_tonemap(const float* f, const float* L, const float* B, const float* mm, float log_contrast,
+                               float detail, float* out, long long plane, hipStream_t st) {
+  hipLaunchKernelGGL(k_tonemap, dim3(grid_for(plane)), dim3(kThreads), 0, st, f, L, B, mm, log_contrast, detail, out,
+                     plane);
   return hipGetLastError();
 }
 

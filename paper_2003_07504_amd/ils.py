@@ -174,6 +174,23 @@ class Plan:
               "ils_smooth_luminance")
         return out
 
+    def tone_map(self, f: torch.Tensor, lam: float = 10.0, p: float = 1.0, eps: float = 1e-4, N: int = 4,
+                 contrast: float = 100.0, detail: float = 1.0, out: torch.Tensor | None = None) -> torch.Tensor:
+        """Single-scale HDR tone mapping of a (3, H, W) linear RGB frame on log luminance."""
+        fc = _as_chw(f, "f")
+        if fc.shape[0] != 3:
+            raise ValueError("tone_map needs a (3, H, W) RGB frame")
+        out = torch.empty_like(f) if out is None else out
+        oc = _as_chw(out, "out")
+        if oc.shape != fc.shape:
+            raise ValueError("out must have the shape of f")
+        _, H, W = fc.shape
+        self._bind_stream()
+        check(self._lib.ils_tone_map(self._h, ctypes.c_void_p(fc.data_ptr()), H, W, float(lam), float(p), float(eps),
+                                     int(N), float(contrast), float(detail), ctypes.c_void_p(oc.data_ptr())),
+              "ils_tone_map")
+        return out
+
     def energy(self, f: torch.Tensor, u: torch.Tensor, lam: float, p: float | None = None, eps: float = 1e-4,
                gamma: float | None = None) -> torch.Tensor:
         """Eq. (1) energy (float64 GPU scalar tensor): Charbonnier with p, or

@@ -62,3 +62,13 @@ def texture_image(H: int, W: int, C: int = 3, K: int = 30, amp: float = 0.2, sig
     img = inten[:, label] + amp * stripes[None] + sigma * rng.standard_normal((C, H, W))
     np.clip(img, 0.0, 1.0, out=img)
     return np.ascontiguousarray(img, dtype=np.float32)
+
+
+def hdr_image(H: int, W: int, K: int = 60, decades: float = 4.0, sigma: float = 0.02, seed: int = 0) -> np.ndarray:
+    """float32 (3, H, W) linear radiance spanning about `decades` orders of
+    magnitude: 10 ** (decades * v) of a colour Voronoi image v (cells in
+    [0, 1), N(0, sigma^2) detail, clipped to [0, 1]).  Stand-in for the HDR
+    radiance maps the paper tone-maps."""
+    from .voronoi import voronoi_image
+    v = voronoi_image(H, W, 3, K, sigma, seed=seed).astype(np.float64)
+    return np.ascontiguousarray(10.0 ** (decades * v), dtype=np.float32)

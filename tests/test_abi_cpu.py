@@ -206,3 +206,7 @@ def test_application_entry_points_reject_bad_arguments(L):
 
 def test_iterate_from_c_rejects_null_plan(L):
     assert L.ils_iterate_from_c(None, None, None, 8, 8, 1, 1.0, 0.8, 1e-4, 201.0, 4, None) == -1
+
+
+def test_tone_map_rejects_null_plan(L):
+    assert L.ils_tone_map(None, None, 8, 8, 10.0, 1.0, 1e-4, 4, 100.0, 1.0, None) == -1

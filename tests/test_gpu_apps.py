@@ -169,3 +169,34 @@ def test_explicit_c_parity_and_convergence_order(torch, ils):
     with pytest.raises(Exception):
         plan.iterate_from(ft, ft, lam, p, eps, N, c=0.9 * c0)
     plan.close()
+
+
+@pytest.mark.parametrize("H,W,contrast,detail", [(64, 96, 100.0, 1.0), (256, 256, 50.0, 1.5), (1080, 1920, 100.0, 1.0)])
+def test_tone_map_parity(torch, ils, H, W, contrast, detail):
+    """HDR tone mapping (lambda = 10, p = 1) against the oracle: relative
+    error of every output value (the smoothing error of the log-luminance
+    base enters through one exp)."""
+    from synth import hdr_image
+    _say(f"tone map H={H} W={W} contrast={contrast} detail={detail}")
+    f = hdr_image(H, W, K=max(4, H * W // 5000), seed=51 + H)
+    ref = O.tone_map(f.astype(np.float64), 10.0, 1.0, 1e-4, 4, contrast=contrast, detail=detail)
+    plan = ils.Plan(H, W, 3)
+    out = plan.tone_map(torch.from_numpy(f).cuda(), 10.0, 1.0, 1e-4, 4, contrast, detail)
+    torch.cuda.synchronize()
+    assert plan.last_error() == 0
+    rel = np.abs(out.cpu().numpy().astype(np.float64) - ref) / ref
+    _say(f"  max rel {rel.max():.2e} mean rel {rel.mean():.2e}")
+    assert rel.max() < 2e-4, rel.max()
+    plan.close()
+
+
+def test_tone_map_rejects_bad_contrast(torch, ils):
+    f = torch.ones((3, 64, 64), device="cuda")
+    plan = ils.Plan(64, 64, 3)
+    for c in (1.0, 0.5, float("inf")):
+        with pytest.raises(Exception):
+            plan.tone_map(f, 10.0, 1.0, 1e-4, 4, c, 1.0)
+    out = plan.tone_map(f, 10.0, 1.0, 1e-4, 4, 100.0, 1.0)  # flat base: luminance normalised to 1
+    torch.cuda.synchronize()
+    assert abs(float(out.mean()) - 1.0) < 1e-5
+    plan.close()

@@ -429,3 +429,29 @@ def test_energy_matches_direct_sum():
             gy = u[(y + 1) % H, x] - u[y, x]
             direct += (u[y, x] - f[y, x]) ** 2 + lam * ((gx * gx + eps) ** (p / 2) + (gy * gy + eps) ** (p / 2))
     assert abs(O.energy(u, f, lam, p, eps) - direct) < 1e-12 * direct
+
+
+def test_tone_map_properties():
+    """Colour ratios of every pixel are kept; the output base spans exactly
+    log(contrast) with maximum 0; with detail = 1 and a contrast equal to the
+    base's own range the map is a pure exposure scale f * exp(-max B)."""
+    from synth import hdr_image
+    f = hdr_image(16, 24, K=6, seed=3).astype(np.float64)
+    out = O.tone_map(f, 10.0, 1.0, 1e-4, 4, contrast=50.0, detail=1.5)
+    ratio = out / f
+    assert np.max(np.abs(ratio - ratio[0:1])) < 1e-12 * np.max(np.abs(ratio))
+    y = np.maximum(O.luma(f), O.LUMA_FLOOR)
+    L = np.log(y)
+    B = O.ils(L, 10.0, 1.0, 1e-4, 4)
+    lo = np.log(np.maximum(O.luma(out), 1e-300))
+    base_out = lo - 1.5 * (L - B)
+    assert abs(base_out.max()) < 1e-9 and abs((base_out.max() - base_out.min()) - np.log(50.0)) < 1e-9
+    rng = float(B.max() - B.min())
+    same = O.tone_map(f, 10.0, 1.0, 1e-4, 4, contrast=float(np.exp(rng)), detail=1.0)
+    assert np.max(np.abs(same - f * np.exp(-B.max())) / (f * np.exp(-B.max()))) < 1e-9
+
+
+def test_tone_map_constant_image_normalises_luminance():
+    f = np.ones((3, 8, 8)) * np.array([2.0, 4.0, 8.0])[:, None, None]
+    out = O.tone_map(f, 10.0, 1.0, 1e-4, 4)
+    assert np.max(np.abs(O.luma(out) - 1.0)) < 1e-12
