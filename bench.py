@@ -245,7 +245,8 @@ def stress_4k_figures(say, reps=2, distinct=8):
 
 def application_figures(ring, say, reps=32):
     """Per-frame time of the applications on the 1080p RGB ring (luminance-only
-    smoothing, detail enhancement k = 3) and of the Welsch-penalty smoother at
+    smoothing, detail enhancement k = 3, HDR tone mapping of a synthetic
+    radiance map) and of the Welsch-penalty smoother at
     the paper's clip-art (lambda 20, gamma 10/255, N 10) and texture (lambda 30,
     gamma 10/255, N 15) settings on the nearest compiled sizes."""
     import torch
@@ -271,6 +272,10 @@ def application_figures(ring, say, reps=32):
     res["luminance_only_1080p_rgb_n4"] = {"ms_per_frame": round(t * 1e3, 4), "Mpixel_s": round(H * W / t / 1e6, 1)}
     t = per_frame(lambda i: plan.detail_enhance(ring[i % len(ring)], 1.0, 0.8, 1e-4, 4, 3.0, out=out), reps)
     res["detail_enhance_k3_1080p_rgb_n4"] = {"ms_per_frame": round(t * 1e3, 4), "Mpixel_s": round(H * W / t / 1e6, 1)}
+    from synth import hdr_image
+    hdr = torch.from_numpy(hdr_image(H, W, K=400, seed=9)).cuda()
+    t = per_frame(lambda i: plan.tone_map(hdr, 10.0, 1.0, 1e-4, 4, 100.0, 1.0, out=out), reps)
+    res["tone_map_1080p_rgb_lambda10_p1_n4"] = {"ms_per_frame": round(t * 1e3, 4), "Mpixel_s": round(H * W / t / 1e6, 1)}
     plan.close()
     for name, (Hh, Ww, lam, gam, N, img) in {
             "welsch_clipart_540x1024_rgb_n10": (540, 1024, 20.0, 10 / 255, 10, clipart_image(540, 1024, 3, seed=7)),
