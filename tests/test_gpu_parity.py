@@ -54,7 +54,7 @@ def _gpu_smooth(torch, ils, f, lam, p, eps, N):
 
 # ------------------------------------------------------------ single passes
 @pytest.mark.parametrize("H,W,C", [(8, 8, 1), (16, 16, 2), (90, 120, 1), (256, 256, 1), (1080, 1920, 1),
-                                   (2160, 3840, 1)])
+                                   (2160, 3840, 1), (480, 640, 1), (720, 1280, 1)])
 def test_stage_rhs_spectrum(torch, ils, H, W, C):
     _say(f"stage rhs H={H} W={W} C={C}")
     lam, p, eps = 1.3, 0.7, 1e-4
@@ -99,7 +99,7 @@ def test_stage_column_solve(torch, ils, H, W, C):
 
 
 @pytest.mark.parametrize("H,W,C", [(8, 8, 1), (16, 16, 1), (90, 120, 2), (256, 256, 1), (1080, 1920, 1),
-                                   (2160, 3840, 1)])
+                                   (2160, 3840, 1), (480, 640, 1), (720, 1280, 1)])
 def test_stage_row_inverse(torch, ils, H, W, C):
     _say(f"stage row inverse H={H} W={W} C={C}")
     rng = np.random.default_rng(H * 3 + W)
@@ -408,4 +408,56 @@ def test_tune_cache_file_is_read_and_written(torch, ils, tmp_path, monkeypatch):
     # a fresh plan reads the appended line and returns the same shapes untimed
     plan = ils.Plan(720, 1280, 1)
     assert plan.tune(720, 1280, 1) == (r, c)
+    plan.close()
+
+
+def test_nan_in_input_propagates_and_leaves_other_frames_alone(torch, ils):
+    """NaN in f is not checked for: it spreads through the transforms of its
+    own channel; the other channel of the frame and the other frame of a batch
+    are unaffected and equal their clean results."""
+    H, W = 64, 96
+    f = voronoi_image(H, W, 2, 8, 0.05, seed=3)
+    g = voronoi_image(H, W, 2, 8, 0.05, seed=4)
+    bad = f.copy()
+    bad[0, 10, 20] = np.nan
+    plan = ils.Plan(H, W, 2, max_frames=2)
+    ft, gt, bt = (torch.from_numpy(x).cuda() for x in (f, g, bad))
+    clean_f = plan.smooth(ft, 1.0, 0.8, 1e-4, 4).cpu().numpy()
+    clean_g = plan.smooth(gt, 1.0, 0.8, 1e-4, 4).cpu().numpy()
+    outs = plan.smooth_batch([(bt, 1.0, 0.8, 1e-4, 4), (gt, 1.0, 0.8, 1e-4, 4)])
+    torch.cuda.synchronize()
+    a, b = outs[0].cpu().numpy(), outs[1].cpu().numpy()
+    assert np.isnan(a[0]).all()
+    assert np.array_equal(a[1], clean_f[1])
+    assert np.array_equal(b, clean_g)
+    plan.close()
+
+
+def test_batch_order_does_not_change_results(torch, ils):
+    """Each frame's result is independent of its position in the batch."""
+    sizes = [(90, 120, 1), (64, 96, 3), (90, 120, 3), (64, 96, 1)]
+    fs = [torch.from_numpy(voronoi_image(H, W, C, 8, 0.05, seed=60 + i)).cuda() for i, (H, W, C) in enumerate(sizes)]
+    params = [(1.0, 0.8, 4), (2.0, 0.5, 3), (0.7, 1.0, 4), (1.3, 0.6, 2)]
+    plan = ils.Plan(90, 120, 3, max_frames=4)
+    frames = [(fs[i], params[i][0], params[i][1], 1e-4, params[i][2]) for i in range(4)]
+    first = [o.cpu().numpy() for o in plan.smooth_batch(frames)]
+    order = [2, 0, 3, 1]
+    second = plan.smooth_batch([frames[i] for i in order])
+    torch.cuda.synchronize()
+    for j, i in enumerate(order):
+        assert np.array_equal(second[j].cpu().numpy(), first[i]), i
+    plan.close()
+
+
+def test_corrupt_tune_cache_is_ignored(torch, ils, tmp_path, monkeypatch):
+    cache = tmp_path / "tune.txt"
+    cache.write_text("garbage line\n\x00\x01 not numbers 7 7\ngfx950 1080 1920\n")
+    monkeypatch.setenv("ILS_TUNE_CACHE", str(cache))
+    f = voronoi_image(90, 120, 1, 8, 0.05, seed=1)
+    plan = ils.Plan(90, 120, 1)
+    u = plan.smooth(torch.from_numpy(f).cuda(), 1.0, 0.8, 1e-4, 4)
+    torch.cuda.synchronize()
+    assert plan.last_error() == 0
+    ref = O.ils_channels(f.astype(np.float64), 1.0, 0.8, 1e-4, 4)
+    assert _errs(u.cpu().numpy(), ref)[0] <= MAX_ABS
     plan.close()

@@ -455,3 +455,17 @@ def test_tone_map_constant_image_normalises_luminance():
     f = np.ones((3, 8, 8)) * np.array([2.0, 4.0, 8.0])[:, None, None]
     out = O.tone_map(f, 10.0, 1.0, 1e-4, 4)
     assert np.max(np.abs(O.luma(out) - 1.0)) < 1e-12
+
+
+def test_generators_are_deterministic_and_in_range():
+    """Same seed, same image; values in [0, 1]; the Voronoi cells are really
+    there (distinct intensity levels close to K when the noise is off)."""
+    from synth import voronoi_image, clipart_image, texture_image
+    a = voronoi_image(40, 60, 3, 12, 0.05, seed=9)
+    b = voronoi_image(40, 60, 3, 12, 0.05, seed=9)
+    assert np.array_equal(a, b) and a.min() >= 0.0 and a.max() <= 1.0
+    assert not np.array_equal(a, voronoi_image(40, 60, 3, 12, 0.05, seed=10))
+    flat = voronoi_image(80, 80, 1, 12, 0.0, seed=9)
+    assert 8 <= len(np.unique(flat)) <= 12  # cells whose centre owns no pixel can vanish
+    assert np.array_equal(clipart_image(32, 40, 3, seed=2), clipart_image(32, 40, 3, seed=2))
+    assert np.array_equal(texture_image(32, 40, 3, seed=2), texture_image(32, 40, 3, seed=2))
