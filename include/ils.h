@@ -175,7 +175,7 @@ int ils_energy_welsch(ils_plan* plan, const float* f, const float* u, int H, int
 
 /* As ils_smooth but starting from u^0 = u0 while the data term stays f
  * (N iterations of Eq. (7)-(9)).  With N = 1 this is the one-iteration map
- * T(u0) used to judge a candidate output by its fixed-point residual.
+ * T(u0) used to assess a candidate output by its fixed-point residual.
  * u0 may equal f; out must not overlap f or u0 unless out == f == u0. */
 int ils_iterate_from(ils_plan* plan, const float* f, const float* u0, int H, int W, int C,
                      float lambda, float p, float eps, int N, float* out);

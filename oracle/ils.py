@@ -239,7 +239,7 @@ def dense_ls_step(u, f, lam, p, eps=1e-4):
 
 
 # --------------------------------------------------------------------------
-# Fixed-point residual used to judge a candidate output
+# Fixed-point residual used to assess a candidate output
 # --------------------------------------------------------------------------
 def fixed_point_residual(v, f, lam, p, eps=1e-4, workers=None):
     """RMS over all pixels of T(v) - v, where T is one ILS iteration started
