@@ -172,23 +172,11 @@ template <int P, int Q>
 constexpr int col_tile() {
   return ColGeom<P, Q, 16>::fits ? 16 : ColGeom<P, Q, 8>::fits ? 8 : 4;
 }
-// The i-th narrower tile: widths 12, 8, 6, 4 below the default, in that
-// order (6 lets two workgroups share a CU where 8 does not fit twice).
-template <int P, int Q>
-constexpr int col_fits_w(int S) {
-  return S == 12 ? ColGeom<P, Q, 12>::fits : S == 8 ? ColGeom<P, Q, 8>::fits
-       : S == 6 ? ColGeom<P, Q, 6>::fits : ColGeom<P, Q, 4>::fits;
-}
 template <int P, int Q, int i>
 constexpr int col_tile_alt() {
   constexpr int w = col_tile<P, Q>();
-  int seen = 0;
-  for (int S : {12, 8, 6, 4})
-    if (S < w && col_fits_w<P, Q>(S)) {
-      if (seen == i) return S;
-      ++seen;
-    }
-  return w;
+  constexpr int cand[3] = {w == 16 ? 12 : 4, 8, 4};
+  return ColGeom<P, Q, cand[i]>::fits && cand[i] < w ? cand[i] : w;
 }
 
 // exp(+- i pi m / n) as a compile-time complex constant.
