@@ -175,6 +175,41 @@ def surrogate_gain(ring, H, W, weights, say):
     return res
 
 
+def small_image_figures(say, reps=200):
+    """256 x 256 grey, N = 4 (lambda = 1, p = 0.8): a latency-bound size.
+    Per image: calls queued back to back, one-frame batches replayed as a HIP
+    graph, and a call followed by a stream synchronisation."""
+    import torch
+
+    from paper_2003_07504_amd import ils
+    from synth import voronoi_image
+
+    f = torch.from_numpy(voronoi_image(256, 256, 1, 40, 0.05, seed=0)).cuda()
+    out = torch.empty_like(f)
+    plan = ils.Plan(256, 256, 1)
+    res = {}
+
+    def timeit(fn, sync_each=False):
+        for _ in range(10):
+            fn()
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(reps):
+            fn()
+            if sync_each:
+                torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - a) / reps * 1e6
+
+    res["queued_us_per_image"] = round(timeit(lambda: plan.smooth(f, 1.0, 0.8, 1e-4, 4, out=out)), 2)
+    res["graph_batch_of_1_us_per_image"] = round(timeit(
+        lambda: plan.smooth_batch([(f, 1.0, 0.8, 1e-4, 4)], outs=[out])), 2)
+    res["synchronous_us_per_call"] = round(timeit(lambda: plan.smooth(f, 1.0, 0.8, 1e-4, 4, out=out), True), 2)
+    plan.close()
+    say(f"256x256 grey N=4: {res}")
+    return res
+
+
 def batch_mix_figures(say, reps=3):
     """Uneven-size batch: 64 frames drawn from {640x480, 1280x720, 1920x1080,
     3840x2160} x {grey, RGB} with per-frame lambda ~ U[0.5, 2], p ~ U[0.5, 1],
@@ -408,6 +443,8 @@ def main():
                                       "Mpixel_s": round(H * W / bt / 1e6, 1)}
         say("uneven-size batch of 64 frames")
         extras["batch_mix_64"] = batch_mix_figures(say)
+        say("256x256 grey latency figures")
+        extras["small_256x256_grey_n4"] = small_image_figures(say)
         say("applications (luminance mode, detail enhancement, Welsch penalty)")
         extras["applications"] = application_figures(ring, say)
         say("4K RGB N=10 stress batch of 32 frames")
