@@ -178,7 +178,8 @@ def surrogate_gain(ring, H, W, weights, say):
 def small_image_figures(say, reps=200):
     """256 x 256 grey, N = 4 (lambda = 1, p = 0.8): a latency-bound size.
     Per image: calls queued back to back, one-frame batches replayed as a HIP
-    graph, and a call followed by a stream synchronisation."""
+    graph, and a call followed by a stream synchronisation.  Also one grey
+    1080p frame per call (a third of the RGB work on the same grid shape)."""
     import torch
 
     from paper_2003_07504_amd import ils
@@ -206,6 +207,13 @@ def small_image_figures(say, reps=200):
         lambda: plan.smooth_batch([(f, 1.0, 0.8, 1e-4, 4)], outs=[out])), 2)
     res["synchronous_us_per_call"] = round(timeit(lambda: plan.smooth(f, 1.0, 0.8, 1e-4, 4, out=out), True), 2)
     plan.close()
+    g = torch.from_numpy(voronoi_image(1080, 1920, 1, 400, 0.05, seed=1)).cuda()
+    og = torch.empty_like(g)
+    pg = ils.Plan(1080, 1920, 1)
+    t = timeit(lambda: pg.smooth(g, 1.0, 0.8, 1e-4, 4, out=og)) * 1e-6
+    res["grey_1080p_n4_Mpixel_s"] = round(1920 * 1080 / t / 1e6, 1)
+    res["grey_1080p_tile_shapes"] = pg.tune(1080, 1920, 1)
+    pg.close()
     say(f"256x256 grey N=4: {res}")
     return res
 

@@ -216,7 +216,7 @@ int ils_profile_end(ils_plan* plan, double* total_ms, int* count);
 int ils_last_error(ils_plan* plan);
 
 /* ---- tile shapes (the autotuner) ----
- * Transform lengths of 480 and more are compiled with up to four row-band
+ * Transform lengths of 480 and more are compiled with up to six row-band
  * heights (rows per workgroup of the row passes) and up to four column-tile
  * widths (spectrum columns per workgroup of the column pass).  Every shape runs the
  * same arithmetic on every row and column, so the results are bitwise equal;
@@ -230,7 +230,7 @@ int ils_last_error(ils_plan* plan);
  * appends new ones.
  *
  * ils_shape_variants: number of row / column shapes for a supported size
- *   (each 1 to 4).  ILS_ERR_UNSUPPORTED_SIZE otherwise.
+ *   (1 to 6 and 1 to 4).  ILS_ERR_UNSUPPORTED_SIZE otherwise.
  * ils_plan_tune: tune the size now if it is not yet (synchronises the
  *   plan's stream) and return the chosen shape indices (0 = default).
  * ils_plan_set_shapes: fix the shapes for a size (indices below the counts

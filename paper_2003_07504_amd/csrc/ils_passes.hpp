@@ -109,8 +109,9 @@ constexpr int row_band() {
 }
 
 // Alternatives offered to the tuner: one workgroup per CU with the largest
-// band that fits (fewest halo rows per output row), and bands of about 3/4
-// and 5/8 of it, which split a frame into fewer blocks than CUs more evenly.
+// band that fits (fewest halo rows per output row), bands of about 3/4 and
+// 5/8 of it, which split a frame into fewer blocks than CUs more evenly, and
+// bands of 5 and 4 rows for frames with few rows in all.
 template <int P, int Q>
 constexpr int row_band_max() {
   constexpr int slot = 4 * RowGeom<P, Q>::SLOT_F;
@@ -124,7 +125,9 @@ constexpr int row_band_max() {
 template <int P, int Q, int i>
 constexpr int row_band_alt() {
   constexpr int gm = row_band_max<P, Q>();
-  return i == 0 ? gm : i == 1 ? (3 * gm + 2) / 4 : (5 * gm + 4) / 8;
+  // i = 3, 4: short bands (5 and 4 rows) that spread a one-channel frame
+  // over all CUs
+  return i == 0 ? gm : i == 1 ? (3 * gm + 2) / 4 : i == 2 ? (5 * gm + 4) / 8 : i == 3 ? 5 : 4;
 }
 
 // Column tile of S spectrum columns.  The exchange row of one k1 is padded
