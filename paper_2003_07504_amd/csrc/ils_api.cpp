@@ -337,10 +337,11 @@ static Pick choose(ils_plan* plan, const FrameDesc& d) {
     const char* env = std::getenv("ILS_TUNE");
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     const bool capturing = hipStreamIsCapturing(plan->stream, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone;
-    // a stream under capture cannot be timed: such a call keeps the defaults
-    // and leaves the size untuned
-    if (capturing) return pk;
-    if (!(env && std::strcmp(env, "0") == 0) && !plan->prof_on) {
+    // a stream under capture cannot be timed, and timing launches would
+    // disturb pass profiling: such a call keeps the defaults and leaves the
+    // size untuned
+    if (capturing || plan->prof_on) return pk;
+    if (!(env && std::strcmp(env, "0") == 0)) {
       // time the shapes on the workspace (inputs and outputs point at the
       // second half spectrum: any finite or non-finite data times the same)
       FrameDesc t = d;
