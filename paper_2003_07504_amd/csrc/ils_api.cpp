@@ -389,7 +389,8 @@ static int run_frame(ils_plan* plan, const FrameDesc& d, int N, int pen = ilsk::
   const WorkList wrow = one_frame(d, row_items(pk.rv, ilsk::ROW_MID, d));
   const WorkList wfin = one_frame(d, row_items(pk.rv, ilsk::ROW_FINAL, d));
   const WorkList wcol = one_frame(d, col_items(pk.cv, d));
-  hipError_t e = timed(plan, 0, [&] { return pk.rv->launch(ilsk::ROW_FIRST, pen, wrow, st); });
+  const int first = (d.f == d.u0) ? ilsk::ROW_FIRST_SAME : ilsk::ROW_FIRST;
+  hipError_t e = timed(plan, 0, [&] { return pk.rv->launch(first, pen, wrow, st); });
   for (int n = 0; n < N && e == hipSuccess; ++n) {
     e = timed(plan, 3, [&] { return pk.cv->launch(wcol, st); });
     if (e != hipSuccess) break;
@@ -913,7 +914,7 @@ int ils_smooth_batch(ils_plan* plan, const ils_frame* frames, int n) {
   };
   struct Launch {
     Pick pk;
-    int N, pen;
+    int N, pen, first;
     WorkList row, fin, col;
   };
   std::vector<Launch> launches;
@@ -932,6 +933,10 @@ int ils_smooth_batch(ils_plan* plan, const ils_frame* frames, int n) {
     L.pk = choose(plan, tdesc);
     L.N = cl.N;
     L.pen = cl.pen;
+    // the first pass reads the data term as u^0 when every frame of the class has u^0 = f
+    L.first = ilsk::ROW_FIRST_SAME;
+    for (int i : cl.idx)
+      if (descs[i].u0 != descs[i].f) L.first = ilsk::ROW_FIRST;
     std::vector<FrameDesc> cd;
     std::vector<int> srow(1, 0), sfin(1, 0), scol(1, 0);
     for (int i : cl.idx) {
@@ -972,7 +977,7 @@ int ils_smooth_batch(ils_plan* plan, const ils_frame* frames, int n) {
   auto enqueue = [&](hipStream_t st) -> hipError_t {
     hipError_t r = hipSuccess;
     for (const Launch& L : launches) {
-      r = timed(plan, 0, [&] { return L.pk.rv->launch(ilsk::ROW_FIRST, L.pen, L.row, st); });
+      r = timed(plan, 0, [&] { return L.pk.rv->launch(L.first, L.pen, L.row, st); });
       if (r != hipSuccess) return r;
     }
     for (int n = 0; n < maxN; ++n) {
@@ -1004,6 +1009,7 @@ int ils_smooth_batch(ils_plan* plan, const ils_frame* frames, int n) {
     sig.push_back((long long)(uintptr_t)L.pk.cv);
     sig.push_back(L.N);
     sig.push_back(L.pen);
+    sig.push_back(L.first);
     sig.push_back(L.row.n);
     sig.push_back(L.row.total);
     sig.push_back(L.fin.total);

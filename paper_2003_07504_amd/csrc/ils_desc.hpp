@@ -37,6 +37,8 @@ struct FrameDesc {
                     // (detail enhancement); 0 writes u
 };
 
-enum RowMode : int { ROW_FIRST = 0, ROW_MID = 1, ROW_FINAL = 2 };
+// ROW_FIRST_SAME is the first pass when u^0 and f are the same image (the
+// data term is then read once, as u^0).
+enum RowMode : int { ROW_FIRST = 0, ROW_MID = 1, ROW_FINAL = 2, ROW_FIRST_SAME = 3 };
 
 }  // namespace ilsk

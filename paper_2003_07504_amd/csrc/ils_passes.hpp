@@ -304,8 +304,8 @@ __device__ __forceinline__ void row_body(const FrameDesc& d, int band, int ch, f
 
   float2 fv[P];
   // u^0 = f (Algorithm 1): the data term is the slot's own u row in LDS
-  const bool f_is_u0 = (MODE == ROW_FIRST) && (d.f == d.u0);
-  if constexpr (MODE == ROW_FIRST) {
+  constexpr bool f_is_u0 = (MODE == ROW_FIRST_SAME);
+  if constexpr (MODE == ROW_FIRST || MODE == ROW_FIRST_SAME) {
     if (in_slot && lane < Q) {  // u^0 row of this slot, all loads in flight together
       const float2* urow = reinterpret_cast<const float2*>(d.u0 + (size_t)ch * H * W + (size_t)yrow * W);
       float2 uv[P];

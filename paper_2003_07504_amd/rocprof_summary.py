@@ -22,7 +22,7 @@ import sqlite3
 from .build import source_hash
 
 COPY_BYTES = 1 << 29
-KINDS = {"0": "row_first", "1": "row_mid", "2": "row_final"}
+KINDS = {"0": "row_first", "1": "row_mid", "2": "row_final", "3": "row_first"}
 
 
 def kind_of(name: str) -> str:
