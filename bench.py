@@ -206,13 +206,6 @@ def small_image_figures(say, reps=200):
     res["graph_batch_of_1_us_per_image"] = round(timeit(
         lambda: plan.smooth_batch([(f, 1.0, 0.8, 1e-4, 4)], outs=[out])), 2)
     res["synchronous_us_per_call"] = round(timeit(lambda: plan.smooth(f, 1.0, 0.8, 1e-4, 4, out=out), True), 2)
-    # device time of the nine passes alone (events around each launch)
-    plan.profile_begin()
-    for _ in range(reps):
-        plan.smooth(f, 1.0, 0.8, 1e-4, 4, out=out)
-    prof = plan.profile_end()
-    torch.cuda.synchronize()
-    res["kernel_us_per_image"] = round(1e3 * sum(t for t, _ in prof.values()) / reps, 2)
     plan.close()
     g = torch.from_numpy(voronoi_image(1080, 1920, 1, 400, 0.05, seed=1)).cuda()
     og = torch.empty_like(g)
