@@ -219,3 +219,50 @@ class Net:
                                             float(tau), out.data_ptr(), scratch.data_ptr(), res.ctypes.data,
                                             fb.ctypes.data), "ils_surrogate_infer")
         return out, res, fb.astype(bool)
+
+
+def _main():
+    """Time the network's forward pass on a batch of synthetic frames:
+    python -m paper_2003_07504_amd.surrogate [--batch 16] [--size 1080x1920] [--reps 20]"""
+    import argparse
+    import json
+    import os
+    import sys
+    import time
+
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--size", default="1080x1920")
+    ap.add_argument("--reps", type=int, default=20)
+    ap.add_argument("--weights", default=os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights",
+                                                      "surrogate.npz"))
+    a = ap.parse_args()
+    H, W = (int(v) for v in a.size.split("x"))
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    if root not in sys.path:
+        sys.path.insert(0, root)
+    from synth import voronoi_image
+    dev = torch.device("cuda:0")
+    f = torch.stack([torch.from_numpy(voronoi_image(H, W, 3, 400, 0.05, seed=1 + i)) for i in range(a.batch)]).to(dev)
+    rng = np.random.default_rng(3)
+    lam = rng.uniform(0.5, 2.0, a.batch).astype(np.float32)
+    p = rng.uniform(0.5, 1.0, a.batch).astype(np.float32)
+    params = np.load(a.weights, allow_pickle=False)["params"] if os.path.exists(a.weights) else None
+    net = Net(a.batch, H, W, device=dev, params=params)
+    out = torch.empty_like(f)
+    net.forward(f, lam, p, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.reps):
+        net.forward(f, lam, p, out=out)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / a.reps
+    macs = sum(9 * ci * co for ci, co in LAYERS) * H * W * a.batch
+    print(json.dumps({"batch": a.batch, "H": H, "W": W, "ms_per_batch": round(dt * 1e3, 3),
+                      "ms_per_frame": round(dt * 1e3 / a.batch, 4),
+                      "TFLOP_s": round(2 * macs / dt / 1e12, 1)}), flush=True)
+    net.close()
+
+
+if __name__ == "__main__":
+    _main()
