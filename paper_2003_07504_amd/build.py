@@ -27,10 +27,14 @@ COMMON = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-Wno-unused-r
 
 
 def source_hash() -> str:
-    """Hash of the kernel sources (identifies the build that counters were taken on)."""
+    """Hash of the sources of the ILS kernels and their host code (identifies
+    the build that the pass counters were taken on).  The surrogate's net_*
+    sources build separate kernels and are left out."""
     import hashlib
     h = hashlib.sha256()
     for name in sorted(os.listdir(CSRC)):
+        if name.startswith("net_"):
+            continue
         if name.endswith((".hip", ".hpp", ".cpp", ".def")):
             with open(os.path.join(CSRC, name), "rb") as fh:
                 h.update(name.encode())
