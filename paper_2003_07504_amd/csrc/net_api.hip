@@ -349,10 +349,24 @@ int rec(ils_net* n, hipError_t e) {
   return ILS_ERR_HIP;
 }
 
+// Workgroups of `kernel` the current device holds at once (the convolution
+// kernels loop over tiles, so a larger grid only adds weight reloads).
+int resident_blocks(const void* kernel) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 1024;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) return 1024;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, NTHREADS, 0) != hipSuccess || per_cu <= 0)
+    per_cu = 1;
+  return cus * per_cu;
+}
+
+int conv_grid(long long tiles, int cap) { return (int)(tiles < cap ? tiles : cap); }
+
 template <int CIP, int COP, int MODE>
 hipError_t conv(const ConvArgs& a, hipStream_t st) {
-  const int blocks = a.B * ((a.H + TH - 1) / TH) * ((a.W + TW - 1) / TW);
-  hipLaunchKernelGGL((k_conv<CIP, COP, MODE>), dim3(blocks), dim3(NTHREADS), 0, st, a);
+  static const int cap = resident_blocks(reinterpret_cast<const void*>(&k_conv<CIP, COP, MODE>));
+  const long long tiles = (long long)a.B * ((a.H + TH - 1) / TH) * ((a.W + TW - 1) / TW);
+  hipLaunchKernelGGL((k_conv<CIP, COP, MODE>), dim3(conv_grid(tiles, cap)), dim3(NTHREADS), 0, st, a);
   return hipGetLastError();
 }
 

@@ -22,12 +22,14 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <utility>
 
 namespace ilsn {
 
 typedef __bf16 bf16;
 typedef bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int TH = 8;   // output rows per convolution block (2 per wave)
 constexpr int TW = 32;  // output columns per block (2 blocks of 16 pixels)
@@ -59,50 +61,99 @@ struct ConvArgs {
   int B, H, W;
 };
 
-template <int CIP, int COP, int MODE>
-__global__ void __launch_bounds__(NTHREADS) k_conv(ConvArgs a) {
-  constexpr int LH = TH + 2, LW = TW + 2;
-  constexpr int KP = kpad(CIP);
-  constexpr int KB = KP / 32;
-  constexpr int MB = COP / 16;
-  constexpr int CH16 = CIP / 8;  // 16-byte chunks per pixel
-  __shared__ __attribute__((aligned(16))) bf16 tile[LH * LW * CIP];
-
-  const int H = a.H, W = a.W;
-  const int tiles_x = (W + TW - 1) / TW, tiles_y = (H + TH - 1) / TH;
-  int bid = blockIdx.x;
-  const int img = bid / (tiles_x * tiles_y);
-  bid -= img * tiles_x * tiles_y;
-  const int ty = bid / tiles_x, tx = bid - ty * tiles_x;
-  const int y0 = ty * TH, x0 = tx * TW;
-  const size_t plane = (size_t)H * W;
-  const bf16* in = a.in + (size_t)img * plane * CIP;
-
-  // halo tile, periodic in both directions
-  for (int i = threadIdx.x; i < LH * LW * CH16; i += NTHREADS) {
-    const int pix = i / CH16, chn = i - pix * CH16;
-    const int ly = pix / LW, lx = pix - ly * LW;
-    const int gy = wrapi(y0 + ly - 1, H), gx = wrapi(x0 + lx - 1, W);
-    *reinterpret_cast<uint4*>(&tile[pix * CIP + chn * 8]) =
-        *reinterpret_cast<const uint4*>(&in[((size_t)gy * W + gx) * CIP + chn * 8]);
+// Tiles: an image is cut into tiles_y x tiles_x output tiles of th x tw
+// pixels; tile t of the batch is image t / (tiles_y tiles_x), row-major
+// within it.  A workgroup takes tiles blockIdx.x, blockIdx.x + gridDim.x, ...
+// (the grid is sized to what the chip holds at once), so that it loads the
+// weight fragments into registers once, and fetches the next tile's halo
+// into registers while it computes on the current one.
+struct TileGrid {
+  int tiles_x, per_img, ntiles, th, tw;
+  __device__ TileGrid(int B, int H, int W, int th_, int tw_) : th(th_), tw(tw_) {
+    tiles_x = (W + tw - 1) / tw;
+    per_img = tiles_x * ((H + th - 1) / th);
+    ntiles = B * per_img;
   }
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  bf16x8 wf[MB][KB];
-#pragma unroll
-  for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-    for (int kb = 0; kb < KB; ++kb)
-      wf[mb][kb] = *reinterpret_cast<const bf16x8*>(&a.wfrag[(mb * 16 + (lane & 15)) * KP + kb * 32 + (lane >> 4) * 8]);
-  __syncthreads();
+  __device__ void origin(int t, int& img, int& y0, int& x0) const {
+    img = t / per_img;
+    const int r = t - img * per_img;
+    const int ty = r / tiles_x;
+    y0 = ty * th;
+    x0 = (r - ty * tiles_x) * tw;
+  }
+};
 
-  f32x4 acc[2][2][MB];
+// LH x LW pixels of CIP channels around (y0 - HALO, x0 - HALO), periodic,
+// held in registers as 16-byte chunks; chunk i goes to LDS element 8 i.
+// Chunk j of a thread is chunk threadIdx.x + j NTHREADS of the tile; every
+// access to r[] has a compile-time index so that r[] stays in registers.
+template <int CIP, int LH, int LW, int HALO>
+struct TileStage {
+  static constexpr int CH16 = CIP / 8;
+  static constexpr int TOTAL = LH * LW * CH16;
+  static constexpr int NLD = (TOTAL + NTHREADS - 1) / NTHREADS;
+  u32x4 r[NLD];
+
+  template <int J>
+  __device__ __forceinline__ void fetch_one(const bf16* in, int H, int W, int y0, int x0) {
+    const int i = threadIdx.x + J * NTHREADS;
+    if (J * NTHREADS + NTHREADS <= TOTAL || i < TOTAL) {
+      const int pix = i / CH16, chn = i - pix * CH16;
+      const int ly = pix / LW, lx = pix - ly * LW;
+      const int gy = wrapi(y0 + ly - HALO, H), gx = wrapi(x0 + lx - HALO, W);
+      r[J] = *reinterpret_cast<const u32x4*>(&in[((size_t)gy * W + gx) * CIP + chn * 8]);
+    }
+  }
+  template <int J>
+  __device__ __forceinline__ void store_one(bf16* tile) const {
+    const int i = threadIdx.x + J * NTHREADS;
+    if (J * NTHREADS + NTHREADS <= TOTAL || i < TOTAL) *reinterpret_cast<u32x4*>(&tile[i * 8]) = r[J];
+  }
+  template <int... J>
+  __device__ __forceinline__ void fetch_all(std::integer_sequence<int, J...>, const bf16* in, int H, int W, int y0,
+                                            int x0) {
+    (fetch_one<J>(in, H, W, y0, x0), ...);
+  }
+  template <int... J>
+  __device__ __forceinline__ void store_all(std::integer_sequence<int, J...>, bf16* tile) const {
+    (store_one<J>(tile), ...);
+  }
+
+  // tile t of the grid, from the batch tensor `in` (B images of H x W)
+  __device__ __forceinline__ void fetch_tile(const TileGrid& tg, const bf16* in, int H, int W, int t) {
+    int img, y0, x0;
+    tg.origin(t, img, y0, x0);
+    fetch_all(std::make_integer_sequence<int, NLD>{}, in + (size_t)img * H * W * CIP, H, W, y0, x0);
+  }
+  __device__ __forceinline__ void store(bf16* tile) const { store_all(std::make_integer_sequence<int, NLD>{}, tile); }
+};
+
+template <int CIP, int COP>
+__device__ __forceinline__ void load_wfrag(const bf16* wfrag, bf16x8 (&wf)[COP / 16][kpad(CIP) / 32]) {
+  constexpr int KP = kpad(CIP);
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int mb = 0; mb < COP / 16; ++mb)
+#pragma unroll
+    for (int kb = 0; kb < KP / 32; ++kb)
+      wf[mb][kb] = *reinterpret_cast<const bf16x8*>(&wfrag[(mb * 16 + (lane & 15)) * KP + kb * 32 + (lane >> 4) * 8]);
+}
+
+// acc[r][nb][mb] = W x X for the output pixels (row0 + r, 16 nb + lane % 16)
+// of a tile in LDS whose rows are LW pixels of CIP channels; the tap (a, c)
+// of output (y, x) reads tile pixel (y + a, x + c).
+template <int CIP, int COP, int LW>
+__device__ __forceinline__ void conv_mfma(const bf16* tile, const bf16x8 (&wf)[COP / 16][kpad(CIP) / 32], int row0,
+                                          f32x4 (&acc)[2][2][COP / 16]) {
+  constexpr int KB = kpad(CIP) / 32;
+  constexpr int MB = COP / 16;
+  const int lane = threadIdx.x & 63;
 #pragma unroll
   for (int r = 0; r < 2; ++r)
 #pragma unroll
     for (int nb = 0; nb < 2; ++nb)
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb) acc[r][nb][mb] = f32x4{0.f, 0.f, 0.f, 0.f};
-
 #pragma unroll
   for (int kb = 0; kb < KB; ++kb) {
     int tap, chunk;
@@ -119,7 +170,7 @@ __global__ void __launch_bounds__(NTHREADS) k_conv(ConvArgs a) {
     for (int r = 0; r < 2; ++r) {
 #pragma unroll
       for (int nb = 0; nb < 2; ++nb) {
-        const int ly = wave * 2 + r + ta;
+        const int ly = row0 + r + ta;
         const int lx = nb * 16 + (lane & 15) + tc;
         const bf16x8 bfr = *reinterpret_cast<const bf16x8*>(&tile[(ly * LW + lx) * CIP + chunk * 8]);
 #pragma unroll
@@ -128,41 +179,85 @@ __global__ void __launch_bounds__(NTHREADS) k_conv(ConvArgs a) {
       }
     }
   }
+}
 
-  // epilogue: lane holds co = mb*16 + 4*(lane/16) + i of pixel (row r, column nb*16 + lane%16)
+template <int CIP, int COP, int MODE>
+__global__ void __launch_bounds__(NTHREADS) k_conv(ConvArgs a) {
+  constexpr int LH = TH + 2, LW = TW + 2;
+  constexpr int MB = COP / 16;
+  constexpr int TILE = LH * LW * CIP;
+  __shared__ __attribute__((aligned(16))) bf16 tile[2 * TILE];  // double-buffered halo tile
+
+  const int H = a.H, W = a.W;
+  const TileGrid tg(a.B, H, W, TH, TW);
+  const size_t plane = (size_t)H * W;
+  const int G = gridDim.x;
+  int t = blockIdx.x;
+  if (t >= tg.ntiles) return;
+  TileStage<CIP, LH, LW, 1> stg;
+  stg.fetch_tile(tg, a.in, H, W, t);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  bf16x8 wf[MB][kpad(CIP) / 32];
+  load_wfrag<CIP, COP>(a.wfrag, wf);
+  float bias[MB][4];
 #pragma unroll
-  for (int r = 0; r < 2; ++r) {
-    const int y = y0 + wave * 2 + r;
+  for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-    for (int nb = 0; nb < 2; ++nb) {
-      const int x = x0 + nb * 16 + (lane & 15);
-      if (y >= H || x >= W) continue;
-      const size_t pix = (size_t)img * plane + (size_t)y * W + x;
+    for (int i = 0; i < 4; ++i) bias[mb][i] = (MODE == CONV_DGRAD) ? 0.0f : a.bias[mb * 16 + 4 * (lane >> 4) + i];
+  stg.store(tile);
+  __syncthreads();
+  int tn = t + G;
+  if (tn < tg.ntiles) stg.fetch_tile(tg, a.in, H, W, tn);
+
+  // The next tile's halo is stored to the other LDS buffer before this
+  // tile's results go out, so that waiting for its loads never waits for
+  // this tile's stores (one counter covers both).
+  for (int cur = 0; t < tg.ntiles; cur ^= 1) {
+    f32x4 acc[2][2][MB];
+    conv_mfma<CIP, COP, LW>(tile + cur * TILE, wf, wave * 2, acc);
+    if (tn < tg.ntiles) stg.store(tile + (cur ^ 1) * TILE);
+
+    int img, y0, x0;
+    tg.origin(t, img, y0, x0);
+    // epilogue: lane holds co = mb*16 + 4*(lane/16) + i of pixel (row r, column nb*16 + lane%16)
 #pragma unroll
-      for (int mb = 0; mb < MB; ++mb) {
-        const int co0 = mb * 16 + 4 * (lane >> 4);
-        const f32x4 d = acc[r][nb][mb];
-        if constexpr (MODE == CONV_RELU) {
-          bf16 o[4];
+    for (int r = 0; r < 2; ++r) {
+      const int y = y0 + wave * 2 + r;
 #pragma unroll
-          for (int i = 0; i < 4; ++i) o[i] = f2bf(fmaxf(d[i] + a.bias[co0 + i], 0.0f));
-          *reinterpret_cast<uint2*>(&a.out[pix * COP + co0]) = *reinterpret_cast<const uint2*>(o);
-        } else if constexpr (MODE == CONV_DGRAD) {
-          const uint2 mraw = *reinterpret_cast<const uint2*>(&a.mask[pix * COP + co0]);
-          const bf16* m = reinterpret_cast<const bf16*>(&mraw);
-          bf16 o[4];
+      for (int nb = 0; nb < 2; ++nb) {
+        const int x = x0 + nb * 16 + (lane & 15);
+        if (y >= H || x >= W) continue;
+        const size_t pix = (size_t)img * plane + (size_t)y * W + x;
 #pragma unroll
-          for (int i = 0; i < 4; ++i) o[i] = f2bf(bf2f(m[i]) > 0.0f ? d[i] : 0.0f);
-          *reinterpret_cast<uint2*>(&a.out[pix * COP + co0]) = *reinterpret_cast<const uint2*>(o);
-        } else {  // CONV_LAST: v = f + z for the three image channels
-          if (co0 == 0) {
-            const size_t base = (size_t)img * 3 * plane + (size_t)y * W + x;
+        for (int mb = 0; mb < MB; ++mb) {
+          const int co0 = mb * 16 + 4 * (lane >> 4);
+          const f32x4 d = acc[r][nb][mb];
+          if constexpr (MODE == CONV_RELU) {
+            bf16 o[4];
 #pragma unroll
-            for (int i = 0; i < 3; ++i) a.v[base + i * plane] = a.f[base + i * plane] + d[i] + a.bias[i];
+            for (int i = 0; i < 4; ++i) o[i] = f2bf(fmaxf(d[i] + bias[mb][i], 0.0f));
+            *reinterpret_cast<uint2*>(&a.out[pix * COP + co0]) = *reinterpret_cast<const uint2*>(o);
+          } else if constexpr (MODE == CONV_DGRAD) {
+            const uint2 mraw = *reinterpret_cast<const uint2*>(&a.mask[pix * COP + co0]);
+            const bf16* m = reinterpret_cast<const bf16*>(&mraw);
+            bf16 o[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) o[i] = f2bf(bf2f(m[i]) > 0.0f ? d[i] : 0.0f);
+            *reinterpret_cast<uint2*>(&a.out[pix * COP + co0]) = *reinterpret_cast<const uint2*>(o);
+          } else {  // CONV_LAST: v = f + z for the three image channels
+            if (co0 == 0) {
+              const size_t base = (size_t)img * 3 * plane + (size_t)y * W + x;
+#pragma unroll
+              for (int i = 0; i < 3; ++i) a.v[base + i * plane] = a.f[base + i * plane] + d[i] + bias[0][i];
+            }
           }
         }
       }
     }
+    __syncthreads();  // the other buffer is complete; every wave is done with this one
+    t = tn;
+    tn = t + G;
+    if (tn < tg.ntiles) stg.fetch_tile(tg, a.in, H, W, tn);
   }
 }
 

@@ -58,7 +58,9 @@ def _batch(B, H, W, seed):
     return f, lam, p
 
 
-@pytest.mark.parametrize("B,H,W", [(2, 8, 32), (1, 16, 48), (2, 12, 20), (1, 5, 7)])
+# (2, 270, 482): more tiles than workgroups in flight, so each workgroup
+# loops over several tiles, with ragged tiles on both edges.
+@pytest.mark.parametrize("B,H,W", [(2, 8, 32), (1, 16, 48), (2, 12, 20), (1, 5, 7), (2, 270, 482)])
 def test_forward_matches_oracle(torch, S, B, H, W):
     _say(f"net forward B={B} H={H} W={W}")
     f, lam, p = _batch(B, H, W, seed=H + W)
