@@ -50,6 +50,9 @@ __device__ __forceinline__ int wrapi(int v, int n) {
   return r < 0 ? r + n : r;
 }
 
+// v mod n for -n <= v < 2n.
+__device__ __forceinline__ int wrap1(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
 struct ConvArgs {
   const bf16* in;       // NHWC, CIP channels
   const bf16* wfrag;    // COP x KP
@@ -94,13 +97,16 @@ struct TileStage {
   static constexpr int NLD = (TOTAL + NTHREADS - 1) / NTHREADS;
   u32x4 r[NLD];
 
-  template <int J>
+  // NEAR: the tile origin is inside the image and the image is at least
+  // LH x LW, so a halo coordinate is off by at most one period.
+  template <int J, bool NEAR>
   __device__ __forceinline__ void fetch_one(const bf16* in, int H, int W, int y0, int x0) {
     const int i = threadIdx.x + J * NTHREADS;
     if (J * NTHREADS + NTHREADS <= TOTAL || i < TOTAL) {
       const int pix = i / CH16, chn = i - pix * CH16;
       const int ly = pix / LW, lx = pix - ly * LW;
-      const int gy = wrapi(y0 + ly - HALO, H), gx = wrapi(x0 + lx - HALO, W);
+      const int gy = NEAR ? wrap1(y0 + ly - HALO, H) : wrapi(y0 + ly - HALO, H);
+      const int gx = NEAR ? wrap1(x0 + lx - HALO, W) : wrapi(x0 + lx - HALO, W);
       r[J] = *reinterpret_cast<const u32x4*>(&in[((size_t)gy * W + gx) * CIP + chn * 8]);
     }
   }
@@ -109,10 +115,10 @@ struct TileStage {
     const int i = threadIdx.x + J * NTHREADS;
     if (J * NTHREADS + NTHREADS <= TOTAL || i < TOTAL) *reinterpret_cast<u32x4*>(&tile[i * 8]) = r[J];
   }
-  template <int... J>
+  template <bool NEAR, int... J>
   __device__ __forceinline__ void fetch_all(std::integer_sequence<int, J...>, const bf16* in, int H, int W, int y0,
                                             int x0) {
-    (fetch_one<J>(in, H, W, y0, x0), ...);
+    (fetch_one<J, NEAR>(in, H, W, y0, x0), ...);
   }
   template <int... J>
   __device__ __forceinline__ void store_all(std::integer_sequence<int, J...>, bf16* tile) const {
@@ -123,7 +129,11 @@ struct TileStage {
   __device__ __forceinline__ void fetch_tile(const TileGrid& tg, const bf16* in, int H, int W, int t) {
     int img, y0, x0;
     tg.origin(t, img, y0, x0);
-    fetch_all(std::make_integer_sequence<int, NLD>{}, in + (size_t)img * H * W * CIP, H, W, y0, x0);
+    in += (size_t)img * H * W * CIP;
+    if (H >= LH && W >= LW)  // uniform over the launch
+      fetch_all<true>(std::make_integer_sequence<int, NLD>{}, in, H, W, y0, x0);
+    else
+      fetch_all<false>(std::make_integer_sequence<int, NLD>{}, in, H, W, y0, x0);
   }
   __device__ __forceinline__ void store(bf16* tile) const { store_all(std::make_integer_sequence<int, NLD>{}, tile); }
 };
@@ -213,12 +223,26 @@ __global__ void __launch_bounds__(NTHREADS) k_conv(ConvArgs a) {
   // tile's results go out, so that waiting for its loads never waits for
   // this tile's stores (one counter covers both).
   for (int cur = 0; t < tg.ntiles; cur ^= 1) {
+    int img, y0, x0;
+    tg.origin(t, img, y0, x0);
+    // CONV_LAST: this tile's f, loaded before the MFMAs so that it arrives during them
+    float fpix[2][2][3];
+    if constexpr (MODE == CONV_LAST) {
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) {
+          const int y = y0 + wave * 2 + r, x = x0 + nb * 16 + (lane & 15);
+          const bool in = (lane >> 4) == 0 && y < H && x < W;
+          const size_t base = (size_t)img * 3 * plane + (size_t)(in ? y : 0) * W + (in ? x : 0);
+#pragma unroll
+          for (int i = 0; i < 3; ++i) fpix[r][nb][i] = in ? a.f[base + i * plane] : 0.0f;
+        }
+    }
     f32x4 acc[2][2][MB];
     conv_mfma<CIP, COP, LW>(tile + cur * TILE, wf, wave * 2, acc);
     if (tn < tg.ntiles) stg.store(tile + (cur ^ 1) * TILE);
 
-    int img, y0, x0;
-    tg.origin(t, img, y0, x0);
     // epilogue: lane holds co = mb*16 + 4*(lane/16) + i of pixel (row r, column nb*16 + lane%16)
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
@@ -248,7 +272,7 @@ __global__ void __launch_bounds__(NTHREADS) k_conv(ConvArgs a) {
             if (co0 == 0) {
               const size_t base = (size_t)img * 3 * plane + (size_t)y * W + x;
 #pragma unroll
-              for (int i = 0; i < 3; ++i) a.v[base + i * plane] = a.f[base + i * plane] + d[i] + bias[0][i];
+              for (int i = 0; i < 3; ++i) a.v[base + i * plane] = fpix[r][nb][i] + d[i] + bias[0][i];
             }
           }
         }
