@@ -364,9 +364,13 @@ int conv_grid(long long tiles, int cap) { return (int)(tiles < cap ? tiles : cap
 
 template <int CIP, int COP, int MODE>
 hipError_t conv(const ConvArgs& a, hipStream_t st) {
-  static const int cap = resident_blocks(reinterpret_cast<const void*>(&k_conv<CIP, COP, MODE>));
+  static const int cap_near = resident_blocks(reinterpret_cast<const void*>(&k_conv<CIP, COP, MODE, true>));
+  static const int cap_any = resident_blocks(reinterpret_cast<const void*>(&k_conv<CIP, COP, MODE, false>));
   const long long tiles = (long long)a.B * ((a.H + TH - 1) / TH) * ((a.W + TW - 1) / TW);
-  hipLaunchKernelGGL((k_conv<CIP, COP, MODE>), dim3(conv_grid(tiles, cap)), dim3(NTHREADS), 0, st, a);
+  if (a.H >= TH + 2 && a.W >= TW + 2)
+    hipLaunchKernelGGL((k_conv<CIP, COP, MODE, true>), dim3(conv_grid(tiles, cap_near)), dim3(NTHREADS), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_conv<CIP, COP, MODE, false>), dim3(conv_grid(tiles, cap_any)), dim3(NTHREADS), 0, st, a);
   return hipGetLastError();
 }
 

@@ -50,6 +50,8 @@ __device__ __forceinline__ int wrapi(int v, int n) {
   return r < 0 ? r + n : r;
 }
 
+__device__ __forceinline__ int imin(int a, int b) { return a < b ? a : b; }
+
 // v mod n for -n <= v < 2n.
 __device__ __forceinline__ int wrap1(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
@@ -64,18 +66,36 @@ struct ConvArgs {
   int B, H, W;
 };
 
+constexpr int kXcds = 8;  // workgroup b of a launch runs on accelerator die b mod 8
+
 // Tiles: an image is cut into tiles_y x tiles_x output tiles of th x tw
 // pixels; tile t of the batch is image t / (tiles_y tiles_x), row-major
-// within it.  A workgroup takes tiles blockIdx.x, blockIdx.x + gridDim.x, ...
-// (the grid is sized to what the chip holds at once), so that it loads the
-// weight fragments into registers once, and fetches the next tile's halo
-// into registers while it computes on the current one.
+// within it.  The grid is sized to what the chip holds at once, so that a
+// workgroup loads the weight fragments into registers once and fetches the
+// next tile's halo into registers while it computes on the current one.
+// Each die takes one contiguous run of tiles (whole stripes of tile rows),
+// walked by its workgroups in step, so that the halo a tile shares with its
+// neighbours above, below and beside it is read once into that die's L2.
 struct TileGrid {
   int tiles_x, per_img, ntiles, th, tw;
   __device__ TileGrid(int B, int H, int W, int th_, int tw_) : th(th_), tw(tw_) {
     tiles_x = (W + tw - 1) / tw;
     per_img = tiles_x * ((H + th - 1) / th);
     ntiles = B * per_img;
+  }
+  // tiles t0, t0 + step, ... below t_end of this workgroup
+  __device__ void span(int& t0, int& t_end, int& step) const {
+    const int G = gridDim.x, b = blockIdx.x;
+    if (G % kXcds == 0) {
+      const int x = b % kXcds, per = (ntiles + kXcds - 1) / kXcds;
+      t0 = x * per + b / kXcds;
+      t_end = per * (x + 1) < ntiles ? per * (x + 1) : ntiles;
+      step = G / kXcds;
+    } else {
+      t0 = b;
+      t_end = ntiles;
+      step = G;
+    }
   }
   __device__ void origin(int t, int& img, int& y0, int& x0) const {
     img = t / per_img;
@@ -97,18 +117,18 @@ struct TileStage {
   static constexpr int NLD = (TOTAL + NTHREADS - 1) / NTHREADS;
   u32x4 r[NLD];
 
-  // NEAR: the tile origin is inside the image and the image is at least
-  // LH x LW, so a halo coordinate is off by at most one period.
+  // Every lane issues every load (past the end of the tile it loads the
+  // tile's last chunk again and does not store it), so that the loads form
+  // one branch-free sequence.  NEAR: the image is at least LH x LW, so a
+  // halo coordinate is off by at most one period.
   template <int J, bool NEAR>
   __device__ __forceinline__ void fetch_one(const bf16* in, int H, int W, int y0, int x0) {
-    const int i = threadIdx.x + J * NTHREADS;
-    if (J * NTHREADS + NTHREADS <= TOTAL || i < TOTAL) {
-      const int pix = i / CH16, chn = i - pix * CH16;
-      const int ly = pix / LW, lx = pix - ly * LW;
-      const int gy = NEAR ? wrap1(y0 + ly - HALO, H) : wrapi(y0 + ly - HALO, H);
-      const int gx = NEAR ? wrap1(x0 + lx - HALO, W) : wrapi(x0 + lx - HALO, W);
-      r[J] = *reinterpret_cast<const u32x4*>(&in[((size_t)gy * W + gx) * CIP + chn * 8]);
-    }
+    const int i = imin(threadIdx.x + J * NTHREADS, TOTAL - 1);
+    const int pix = i / CH16, chn = i - pix * CH16;
+    const int ly = pix / LW, lx = pix - ly * LW;
+    const int gy = NEAR ? wrap1(y0 + ly - HALO, H) : wrapi(y0 + ly - HALO, H);
+    const int gx = NEAR ? wrap1(x0 + lx - HALO, W) : wrapi(x0 + lx - HALO, W);
+    r[J] = *reinterpret_cast<const u32x4*>(&in[((size_t)gy * W + gx) * CIP + chn * 8]);
   }
   template <int J>
   __device__ __forceinline__ void store_one(bf16* tile) const {
@@ -126,14 +146,11 @@ struct TileStage {
   }
 
   // tile t of the grid, from the batch tensor `in` (B images of H x W)
+  template <bool NEAR>
   __device__ __forceinline__ void fetch_tile(const TileGrid& tg, const bf16* in, int H, int W, int t) {
     int img, y0, x0;
     tg.origin(t, img, y0, x0);
-    in += (size_t)img * H * W * CIP;
-    if (H >= LH && W >= LW)  // uniform over the launch
-      fetch_all<true>(std::make_integer_sequence<int, NLD>{}, in, H, W, y0, x0);
-    else
-      fetch_all<false>(std::make_integer_sequence<int, NLD>{}, in, H, W, y0, x0);
+    fetch_all<NEAR>(std::make_integer_sequence<int, NLD>{}, in + (size_t)img * H * W * CIP, H, W, y0, x0);
   }
   __device__ __forceinline__ void store(bf16* tile) const { store_all(std::make_integer_sequence<int, NLD>{}, tile); }
 };
@@ -191,21 +208,27 @@ __device__ __forceinline__ void conv_mfma(const bf16* tile, const bf16x8 (&wf)[C
   }
 }
 
-template <int CIP, int COP, int MODE>
-__global__ void __launch_bounds__(NTHREADS) k_conv(ConvArgs a) {
+// NEAR: the image is at least (TH + 2) x (TW + 2) (chosen by the launcher).
+template <int CIP, int COP, int MODE, bool NEAR>
+__global__ void __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(MODE == CONV_LAST ? 3 : 1))) k_conv(ConvArgs a) {
   constexpr int LH = TH + 2, LW = TW + 2;
   constexpr int MB = COP / 16;
   constexpr int TILE = LH * LW * CIP;
+  // tiles whose halo is in flight in registers (the last layer keeps one so
+  // that three wavefronts per SIMD still fit)
+  constexpr int DEPTH = (MODE == CONV_LAST) ? 1 : 2;
   __shared__ __attribute__((aligned(16))) bf16 tile[2 * TILE];  // double-buffered halo tile
 
   const int H = a.H, W = a.W;
   const TileGrid tg(a.B, H, W, TH, TW);
   const size_t plane = (size_t)H * W;
-  const int G = gridDim.x;
-  int t = blockIdx.x;
-  if (t >= tg.ntiles) return;
-  TileStage<CIP, LH, LW, 1> stg;
-  stg.fetch_tile(tg, a.in, H, W, t);
+  int t, t_end, G;
+  tg.span(t, t_end, G);
+  if (t >= t_end) return;
+  const int last = t_end - 1;
+  using Stage = TileStage<CIP, LH, LW, 1>;
+  Stage st[DEPTH];
+  st[0].template fetch_tile<NEAR>(tg, a.in, H, W, t);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   bf16x8 wf[MB][kpad(CIP) / 32];
   load_wfrag<CIP, COP>(a.wfrag, wf);
@@ -214,15 +237,19 @@ __global__ void __launch_bounds__(NTHREADS) k_conv(ConvArgs a) {
   for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
     for (int i = 0; i < 4; ++i) bias[mb][i] = (MODE == CONV_DGRAD) ? 0.0f : a.bias[mb * 16 + 4 * (lane >> 4) + i];
-  stg.store(tile);
+  st[0].store(tile);
   __syncthreads();
-  int tn = t + G;
-  if (tn < tg.ntiles) stg.fetch_tile(tg, a.in, H, W, tn);
+  // Every prefetch is issued (past the end it repeats the last tile), so
+  // the number of loads in flight behind a stage is the same on every path
+  // and waiting for one stage never waits for the next one's loads.
+#pragma unroll
+  for (int k = 0; k < DEPTH; ++k) st[k].template fetch_tile<NEAR>(tg, a.in, H, W, imin(t + (k + 1) * G, last));
 
-  // The next tile's halo is stored to the other LDS buffer before this
-  // tile's results go out, so that waiting for its loads never waits for
-  // this tile's stores (one counter covers both).
-  for (int cur = 0; t < tg.ntiles; cur ^= 1) {
+  // One tile: t is in LDS buffer cur, nx holds tile t + G.  The next tile's
+  // halo is stored to the other LDS buffer before this tile's results go
+  // out, so that waiting for its loads never waits for this tile's stores
+  // (one counter covers both); nx then fetches tile t + (DEPTH + 1) G.
+  auto step = [&](Stage& nx, int cur) __attribute__((always_inline)) -> bool {
     int img, y0, x0;
     tg.origin(t, img, y0, x0);
     // CONV_LAST: this tile's f, loaded before the MFMAs so that it arrives during them
@@ -241,7 +268,7 @@ __global__ void __launch_bounds__(NTHREADS) k_conv(ConvArgs a) {
     }
     f32x4 acc[2][2][MB];
     conv_mfma<CIP, COP, LW>(tile + cur * TILE, wf, wave * 2, acc);
-    if (tn < tg.ntiles) stg.store(tile + (cur ^ 1) * TILE);
+    if (t + G < t_end) nx.store(tile + (cur ^ 1) * TILE);
 
     // epilogue: lane holds co = mb*16 + 4*(lane/16) + i of pixel (row r, column nb*16 + lane%16)
 #pragma unroll
@@ -279,9 +306,16 @@ __global__ void __launch_bounds__(NTHREADS) k_conv(ConvArgs a) {
       }
     }
     __syncthreads();  // the other buffer is complete; every wave is done with this one
-    t = tn;
-    tn = t + G;
-    if (tn < tg.ntiles) stg.fetch_tile(tg, a.in, H, W, tn);
+    nx.template fetch_tile<NEAR>(tg, a.in, H, W, imin(t + (DEPTH + 1) * G, last));
+    t += G;
+    return t < t_end;
+  };
+  if constexpr (DEPTH == 1) {
+    for (int cur = 0; step(st[0], cur); cur ^= 1) {
+    }
+  } else {
+    while (step(st[0], 0) && step(st[DEPTH - 1], 1)) {
+    }
   }
 }
 
