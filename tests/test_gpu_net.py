@@ -82,9 +82,11 @@ def test_forward_matches_oracle(torch, S, B, H, W):
     net.close()
 
 
-def test_gradients_match_oracle(torch, S):
-    _say("net gradients")
-    B, H, W = 2, 8, 32
+# (1, 270, 482): the convolution instances for images of at least one halo
+# tile, with more tiles than workgroups in flight
+@pytest.mark.parametrize("B,H,W", [(2, 8, 32), (1, 270, 482)])
+def test_gradients_match_oracle(torch, S, B, H, W):
+    _say(f"net gradients B={B} H={H} W={W}")
     f, lam, p = _batch(B, H, W, seed=7)
     t = np.clip(f + 0.05 * np.random.default_rng(8).standard_normal(f.shape), 0, 1).astype(np.float32)
     flat = S.init_params(seed=5)
