@@ -10,7 +10,10 @@
  * float32 (B, 3, H, W), contiguous, device pointers owned by the caller.
  * All calls enqueue on the network's stream and return after enqueue,
  * except ils_net_set_state / ils_net_get_state (synchronous) and
- * ils_surrogate_infer (synchronises once to read the residuals).
+ * ils_surrogate_infer (synchronises once to read the residuals).  The
+ * activations, gradients and optimiser state live in the network's
+ * workspace and are shared by all its calls, so calls on one network must
+ * not overlap (keep them on its stream, from one host thread at a time).
  *
  * Parameter layout (fp32, ils_net_param_count() values): for each layer in
  * order, w[co][ci][3][3] then b[co]; layers 5->32, 32->32 (x4), 32->3.
