@@ -175,6 +175,43 @@ def surrogate_gain(ring, H, W, weights, say):
     return res
 
 
+def two_stream_figures(plan, ring, outs, H, W, C, lam, p, eps, N, shapes, steps):
+    """Frames alternate between two plans on two streams (default priority),
+    so that one frame's passes can use the compute units the other frame's
+    passes leave idle (pass tails, load and store phases).  Each frame still
+    takes the whole path; only two are in flight."""
+    import torch
+
+    from paper_2003_07504_amd import ils
+
+    dev = ring[0].device
+    plan2 = ils.Plan(H, W, C)
+    plan2.set_shapes(H, W, C, shapes["row_shape"], shapes["col_shape"])
+    s1 = torch.cuda.Stream(device=dev)
+    outs2 = [torch.empty_like(f) for f in ring]
+    torch.cuda.synchronize()
+
+    def go(n):
+        for i in range(n):
+            j = i % len(ring)
+            if i % 2 == 0:
+                plan.smooth(ring[j], lam, p, eps, N, out=outs[j])
+            else:
+                with torch.cuda.stream(s1):
+                    plan2.smooth(ring[j], lam, p, eps, N, out=outs2[j])
+
+    go(32)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    go(steps)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - a) / steps
+    if plan2.last_error() != 0:
+        raise RuntimeError("HIP error in the two-stream figure")
+    plan2.close()
+    return {"ms_per_frame": round(dt * 1e3, 4), "fps": round(1 / dt, 1), "Mpixel_s": round(H * W / dt / 1e6, 1)}
+
+
 def small_image_figures(say, reps=200):
     """256 x 256 grey, N = 4 (lambda = 1, p = 0.8): a latency-bound size.
     Per image: calls queued back to back, one-frame batches replayed as a HIP
@@ -477,6 +514,9 @@ def main():
         bt = (time.perf_counter() - a) / (batches * nb)
         extras["batched_8_frames"] = {"ms_per_frame": round(bt * 1e3, 4), "fps": round(1 / bt, 1),
                                       "Mpixel_s": round(H * W / bt / 1e6, 1)}
+        say("two frames in flight on two streams")
+        extras["two_streams_1080p_rgb_n4"] = two_stream_figures(plan, ring, outs, H, W, C, lam, p, eps, N, shapes,
+                                                                args.steps)
         say("uneven-size batch of 64 frames")
         extras["batch_mix_64"] = batch_mix_figures(say)
         say("energy along the iteration (1080p RGB, N up to 30)")
