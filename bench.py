@@ -175,19 +175,16 @@ def surrogate_gain(ring, H, W, weights, say):
     return res
 
 
-def two_stream_figures(plan, ring, outs, H, W, C, lam, p, eps, N, shapes, steps):
+def two_stream_figures(plan, plan2, s1, ring, outs, H, W, C, lam, p, eps, N, shapes, steps):
     """Frames alternate between two plans on two streams (default priority),
     so that one frame's passes can use the compute units the other frame's
     passes leave idle (pass tails, load and store phases).  Each frame still
-    takes the whole path; only two are in flight."""
+    takes the whole path; only two are in flight.  s1 is created before any
+    other stream of the process, so that it does not share a hardware queue
+    with the default stream."""
     import torch
 
-    from paper_2003_07504_amd import ils
-
-    dev = ring[0].device
-    plan2 = ils.Plan(H, W, C)
     plan2.set_shapes(H, W, C, shapes["row_shape"], shapes["col_shape"])
-    s1 = torch.cuda.Stream(device=dev)
     outs2 = [torch.empty_like(f) for f in ring]
     torch.cuda.synchronize()
 
@@ -208,7 +205,6 @@ def two_stream_figures(plan, ring, outs, H, W, C, lam, p, eps, N, shapes, steps)
     dt = (time.perf_counter() - a) / steps
     if plan2.last_error() != 0:
         raise RuntimeError("HIP error in the two-stream figure")
-    plan2.close()
     return {"ms_per_frame": round(dt * 1e3, 4), "fps": round(1 / dt, 1), "Mpixel_s": round(H * W / dt / 1e6, 1)}
 
 
@@ -429,10 +425,12 @@ def main():
     say(f"generating {args.ring} frames {W}x{H}x{C}")
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    s1 = torch.cuda.Stream(device=dev)  # second stream of the two-stream figure, first of the process
     frames_np = [voronoi_image(H, W, C, 400, 0.05, seed=1 + i) for i in range(args.ring)]
     ring = [torch.from_numpy(f).to(dev) for f in frames_np]
     outs = [torch.empty_like(f) for f in ring]
     plan = ils.Plan(H, W, C, max_frames=8)
+    plan2 = ils.Plan(H, W, C)  # the two-stream figure's second plan
     torch.cuda.synchronize()
 
     def run(k0, k):
@@ -515,8 +513,8 @@ def main():
         extras["batched_8_frames"] = {"ms_per_frame": round(bt * 1e3, 4), "fps": round(1 / bt, 1),
                                       "Mpixel_s": round(H * W / bt / 1e6, 1)}
         say("two frames in flight on two streams")
-        extras["two_streams_1080p_rgb_n4"] = two_stream_figures(plan, ring, outs, H, W, C, lam, p, eps, N, shapes,
-                                                                args.steps)
+        extras["two_streams_1080p_rgb_n4"] = two_stream_figures(plan, plan2, s1, ring, outs, H, W, C, lam, p, eps,
+                                                                N, shapes, args.steps)
         say("uneven-size batch of 64 frames")
         extras["batch_mix_64"] = batch_mix_figures(say)
         say("energy along the iteration (1080p RGB, N up to 30)")

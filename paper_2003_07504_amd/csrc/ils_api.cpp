@@ -92,8 +92,11 @@ struct ils_plan {
   hipEvent_t stage_ev[kStageSlots];
   bool stage_used[kStageSlots];
   int stage_next;
-  // graph of the last batched call (replayed while the batch structure repeats)
+  // graph of the last batched call (replayed while the batch structure repeats);
+  // its second chain of passes is captured on cap_stream2, forked and joined by events
   hipStream_t cap_stream;
+  hipStream_t cap_stream2;
+  hipEvent_t fork_ev, join_ev;
   hipGraphExec_t batch_exec;
   std::vector<long long> batch_sig;
   // tile shapes chosen per image size (H, W, C) -> (row variant, column variant)
@@ -158,6 +161,9 @@ static void free_plan(ils_plan* plan) {
   for (hipEvent_t ev : plan->ev_pool) (void)hipEventDestroy(ev);
   if (plan->batch_exec) (void)hipGraphExecDestroy(plan->batch_exec);
   if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
+  if (plan->cap_stream2) (void)hipStreamDestroy(plan->cap_stream2);
+  if (plan->fork_ev) (void)hipEventDestroy(plan->fork_ev);
+  if (plan->join_ev) (void)hipEventDestroy(plan->join_ev);
   for (int i = 0; i < kStageSlots; ++i) {
     if (plan->stage_used[i]) (void)hipEventSynchronize(plan->stage_ev[i]);
     if (plan->stage_ev[i]) (void)hipEventDestroy(plan->stage_ev[i]);
@@ -471,6 +477,9 @@ int ils_plan_create(ils_plan** plan_out, int max_H, int max_W, int max_C, int ma
   plan->prof_on = false;
   plan->ev_used = 0;
   plan->cap_stream = nullptr;
+  plan->cap_stream2 = nullptr;
+  plan->fork_ev = nullptr;
+  plan->join_ev = nullptr;
   plan->batch_exec = nullptr;
   for (int i = 0; i < kStageSlots; ++i) {
     plan->stage[i] = nullptr;
@@ -489,7 +498,10 @@ int ils_plan_create(ils_plan** plan_out, int max_H, int max_W, int max_C, int ma
     load_tune_cache(plan);
   }
   if (!(flags & ILS_PLAN_NO_GRAPH) &&
-      hipStreamCreateWithFlags(&plan->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+      (hipStreamCreateWithFlags(&plan->cap_stream, hipStreamNonBlocking) != hipSuccess ||
+       hipStreamCreateWithFlags(&plan->cap_stream2, hipStreamNonBlocking) != hipSuccess ||
+       hipEventCreateWithFlags(&plan->fork_ev, hipEventDisableTiming) != hipSuccess ||
+       hipEventCreateWithFlags(&plan->join_ev, hipEventDisableTiming) != hipSuccess)) {
     free_plan(plan);
     return ILS_ERR_HIP;
   }
@@ -888,19 +900,42 @@ int ils_smooth_batch(ils_plan* plan, const ils_frame* frames, int n) {
 
   // Group frames into classes of equal (row length, column length, N,
   // penalty): one launch per pass per class, each a grid over the class's
-  // (frame, channel, band) work list.
+  // (frame, channel, band) work list.  The classes are dealt to two
+  // independent chains of passes (a class of several frames is halved
+  // between them), so that the passes of one chain can run on the compute
+  // units the other chain's passes leave idle.
   struct Class {
     int M, H, N, pen;
     std::vector<int> idx;
+    int lane;
   };
-  std::vector<Class> classes;
+  std::vector<Class> grouped;
   for (size_t i = 0; i < descs.size(); ++i) {
     int M = descs[i].W / 2, H = descs[i].H, N = iters[i], pen = pens[i];
     size_t c = 0;
-    for (; c < classes.size(); ++c)
-      if (classes[c].M == M && classes[c].H == H && classes[c].N == N && classes[c].pen == pen) break;
-    if (c == classes.size()) classes.push_back(Class{M, H, N, pen, {}});
-    classes[c].idx.push_back((int)i);
+    for (; c < grouped.size(); ++c)
+      if (grouped[c].M == M && grouped[c].H == H && grouped[c].N == N && grouped[c].pen == pen) break;
+    if (c == grouped.size()) grouped.push_back(Class{M, H, N, pen, {}, 0});
+    grouped[c].idx.push_back((int)i);
+  }
+  std::vector<Class> classes;
+  int next_lane = 0;
+  for (const Class& g : grouped) {
+    const size_t nf = g.idx.size();
+    if (nf >= 2) {
+      Class a = g, b = g;
+      a.idx.assign(g.idx.begin(), g.idx.begin() + nf / 2);
+      b.idx.assign(g.idx.begin() + nf / 2, g.idx.end());
+      a.lane = 0;
+      b.lane = 1;
+      classes.push_back(a);
+      classes.push_back(b);
+    } else {
+      Class a = g;
+      a.lane = next_lane;
+      next_lane ^= 1;
+      classes.push_back(a);
+    }
   }
 
   // Host image of the batch header: per class, descriptors then three start
@@ -914,7 +949,7 @@ int ils_smooth_batch(ils_plan* plan, const ils_frame* frames, int n) {
   };
   struct Launch {
     Pick pk;
-    int N, pen, first;
+    int N, pen, first, lane;
     WorkList row, fin, col;
   };
   std::vector<Launch> launches;
@@ -931,6 +966,7 @@ int ils_smooth_batch(ils_plan* plan, const ils_frame* frames, int n) {
     tdesc.specA = reinterpret_cast<cf*>(base);
     tdesc.specB = reinterpret_cast<cf*>(base + (size_t)ctot * tdesc.H * tdesc.ldS * sizeof(cf));
     L.pk = choose(plan, tdesc);
+    L.lane = cl.lane;
     L.N = cl.N;
     L.pen = cl.pen;
     // the first pass reads the data term as u^0 when every frame of the class has u^0 = f
@@ -973,21 +1009,23 @@ int ils_smooth_batch(ils_plan* plan, const ils_frame* frames, int n) {
 
   int maxN = 0;
   for (const Launch& L : launches) maxN = L.N > maxN ? L.N : maxN;
-  // Pass-major order: every class's pass k is enqueued before any pass k+1.
-  auto enqueue = [&](hipStream_t st) -> hipError_t {
+  // Pass-major order within a chain: every class's pass k is enqueued
+  // before any pass k+1.  Chain `lane` goes to st[lane].
+  auto enqueue_chain = [&](int lane, hipStream_t st) -> hipError_t {
     hipError_t r = hipSuccess;
     for (const Launch& L : launches) {
+      if (L.lane != lane) continue;
       r = timed(plan, 0, [&] { return L.pk.rv->launch(L.first, L.pen, L.row, st); });
       if (r != hipSuccess) return r;
     }
     for (int n = 0; n < maxN; ++n) {
       for (const Launch& L : launches) {
-        if (n >= L.N) continue;
+        if (L.lane != lane || n >= L.N) continue;
         r = timed(plan, 3, [&] { return L.pk.cv->launch(L.col, st); });
         if (r != hipSuccess) return r;
       }
       for (const Launch& L : launches) {
-        if (n >= L.N) continue;
+        if (L.lane != lane || n >= L.N) continue;
         if (n + 1 < L.N)
           r = timed(plan, 1, [&] { return L.pk.rv->launch(ilsk::ROW_MID, L.pen, L.row, st); });
         else
@@ -997,7 +1035,13 @@ int ils_smooth_batch(ils_plan* plan, const ils_frame* frames, int n) {
     }
     return r;
   };
-  if (plan->prof_on || !plan->cap_stream) return record(plan, enqueue(plan->stream));
+  bool two = false;
+  for (const Launch& L : launches) two = two || L.lane == 1;
+  if (plan->prof_on || !plan->cap_stream) {  // both chains in order on the caller's stream
+    e = enqueue_chain(0, plan->stream);
+    if (e == hipSuccess) e = enqueue_chain(1, plan->stream);
+    return record(plan, e);
+  }
 
   // The whole 2N+1-pass sequence as one graph: the kernels read every frame
   // parameter from the work lists in the workspace header, so a replay for a
@@ -1005,6 +1049,7 @@ int ils_smooth_batch(ils_plan* plan, const ils_frame* frames, int n) {
   std::vector<long long> sig;
   sig.push_back((long long)hdr.size());
   for (const Launch& L : launches) {
+    sig.push_back(L.lane);
     sig.push_back((long long)(uintptr_t)L.pk.rv);
     sig.push_back((long long)(uintptr_t)L.pk.cv);
     sig.push_back(L.N);
@@ -1024,7 +1069,19 @@ int ils_smooth_batch(ils_plan* plan, const ils_frame* frames, int n) {
     hipGraph_t g = nullptr;
     e = hipStreamBeginCapture(plan->cap_stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return record(plan, e);
-    hipError_t el = enqueue(plan->cap_stream);
+    // chain 1 forks from the start of the capture and joins before its end,
+    // so the graph holds the two chains as independent branches
+    hipError_t el = hipSuccess;
+    if (two) {
+      el = hipEventRecord(plan->fork_ev, plan->cap_stream);
+      if (el == hipSuccess) el = hipStreamWaitEvent(plan->cap_stream2, plan->fork_ev, 0);
+    }
+    if (el == hipSuccess) el = enqueue_chain(0, plan->cap_stream);
+    if (two) {
+      if (el == hipSuccess) el = enqueue_chain(1, plan->cap_stream2);
+      if (el == hipSuccess) el = hipEventRecord(plan->join_ev, plan->cap_stream2);
+      if (el == hipSuccess) el = hipStreamWaitEvent(plan->cap_stream, plan->join_ev, 0);
+    }
     e = hipStreamEndCapture(plan->cap_stream, &g);
     if (el != hipSuccess) e = el;
     if (e == hipSuccess) e = hipGraphInstantiate(&plan->batch_exec, g, nullptr, nullptr, 0);
