@@ -63,6 +63,10 @@ inline size_t frame_ws_bytes(int H, int W, int C) {
 
 // Device-resident header of the batch work lists (descriptors + starts).
 constexpr size_t kBatchHeaderBytes = 1 << 20;
+constexpr int kChains = 2;  // independent chains of passes in a batch graph
+// Frames of at least this many pixel-channels fill the chip on their own:
+// in a batch each is a part of its own (see ils_smooth_batch).
+constexpr long long kPartPxCh = 1LL << 22;
 constexpr int kMaxBatchFrames = 4096;
 
 }  // namespace
@@ -93,10 +97,11 @@ struct ils_plan {
   bool stage_used[kStageSlots];
   int stage_next;
   // graph of the last batched call (replayed while the batch structure repeats);
-  // its second chain of passes is captured on cap_stream2, forked and joined by events
+  // chain c > 0 of its passes is captured on chain_stream[c], forked from
+  // cap_stream by fork_ev and joined back by join_ev[c]
   hipStream_t cap_stream;
-  hipStream_t cap_stream2;
-  hipEvent_t fork_ev, join_ev;
+  hipStream_t chain_stream[kChains];
+  hipEvent_t fork_ev, join_ev[kChains];
   hipGraphExec_t batch_exec;
   std::vector<long long> batch_sig;
   // tile shapes chosen per image size (H, W, C) -> (row variant, column variant)
@@ -161,9 +166,11 @@ static void free_plan(ils_plan* plan) {
   for (hipEvent_t ev : plan->ev_pool) (void)hipEventDestroy(ev);
   if (plan->batch_exec) (void)hipGraphExecDestroy(plan->batch_exec);
   if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
-  if (plan->cap_stream2) (void)hipStreamDestroy(plan->cap_stream2);
+  for (int c = 1; c < kChains; ++c) {
+    if (plan->chain_stream[c]) (void)hipStreamDestroy(plan->chain_stream[c]);
+    if (plan->join_ev[c]) (void)hipEventDestroy(plan->join_ev[c]);
+  }
   if (plan->fork_ev) (void)hipEventDestroy(plan->fork_ev);
-  if (plan->join_ev) (void)hipEventDestroy(plan->join_ev);
   for (int i = 0; i < kStageSlots; ++i) {
     if (plan->stage_used[i]) (void)hipEventSynchronize(plan->stage_ev[i]);
     if (plan->stage_ev[i]) (void)hipEventDestroy(plan->stage_ev[i]);
@@ -477,9 +484,11 @@ int ils_plan_create(ils_plan** plan_out, int max_H, int max_W, int max_C, int ma
   plan->prof_on = false;
   plan->ev_used = 0;
   plan->cap_stream = nullptr;
-  plan->cap_stream2 = nullptr;
+  for (int c = 0; c < kChains; ++c) {
+    plan->chain_stream[c] = nullptr;
+    plan->join_ev[c] = nullptr;
+  }
   plan->fork_ev = nullptr;
-  plan->join_ev = nullptr;
   plan->batch_exec = nullptr;
   for (int i = 0; i < kStageSlots; ++i) {
     plan->stage[i] = nullptr;
@@ -497,13 +506,17 @@ int ils_plan_create(ils_plan** plan_out, int max_H, int max_W, int max_C, int ma
     if (colon != std::string::npos) plan->arch.resize(colon);
     load_tune_cache(plan);
   }
-  if (!(flags & ILS_PLAN_NO_GRAPH) &&
-      (hipStreamCreateWithFlags(&plan->cap_stream, hipStreamNonBlocking) != hipSuccess ||
-       hipStreamCreateWithFlags(&plan->cap_stream2, hipStreamNonBlocking) != hipSuccess ||
-       hipEventCreateWithFlags(&plan->fork_ev, hipEventDisableTiming) != hipSuccess ||
-       hipEventCreateWithFlags(&plan->join_ev, hipEventDisableTiming) != hipSuccess)) {
-    free_plan(plan);
-    return ILS_ERR_HIP;
+  if (!(flags & ILS_PLAN_NO_GRAPH)) {
+    bool ok = hipStreamCreateWithFlags(&plan->cap_stream, hipStreamNonBlocking) == hipSuccess &&
+              hipEventCreateWithFlags(&plan->fork_ev, hipEventDisableTiming) == hipSuccess;
+    for (int c = 1; c < kChains && ok; ++c)
+      ok = hipStreamCreateWithFlags(&plan->chain_stream[c], hipStreamNonBlocking) == hipSuccess &&
+           hipEventCreateWithFlags(&plan->join_ev[c], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+      free_plan(plan);
+      return ILS_ERR_HIP;
+    }
+    plan->chain_stream[0] = plan->cap_stream;
   }
   for (int i = 0; i < kStageSlots; ++i) {
     if (hipHostMalloc((void**)&plan->stage[i], kStageBytes, hipHostMallocDefault) != hipSuccess ||
@@ -900,14 +913,22 @@ int ils_smooth_batch(ils_plan* plan, const ils_frame* frames, int n) {
 
   // Group frames into classes of equal (row length, column length, N,
   // penalty): one launch per pass per class, each a grid over the class's
-  // (frame, channel, band) work list.  The classes are dealt to two
-  // independent chains of passes (a class of several frames is halved
-  // between them), so that the passes of one chain can run on the compute
-  // units the other chain's passes leave idle.
+  // (frame, channel, band) work list.  A class of frames of one channel
+  // count that each hold at least kPartPxCh pixel-channels is cut into one
+  // part per frame; any other class into min(frames, kChains) parts of
+  // consecutive frames (small frames need the larger grids of a shared
+  // launch, and mixed grey and colour frames would make uneven parts).
+  // Per-frame parts go to the kChains independent chains in turn, and a
+  // chain runs each one's whole pass sequence before the next one's, so the
+  // chains drift out of phase and the passes of one run on the compute
+  // units the other's leave idle; the parts of any other class go to chains
+  // 0, 1, ... and run pass-major, side by side with the other parts of
+  // their class.
   struct Class {
     int M, H, N, pen;
     std::vector<int> idx;
     int lane;
+    bool big;
   };
   std::vector<Class> grouped;
   for (size_t i = 0; i < descs.size(); ++i) {
@@ -915,25 +936,27 @@ int ils_smooth_batch(ils_plan* plan, const ils_frame* frames, int n) {
     size_t c = 0;
     for (; c < grouped.size(); ++c)
       if (grouped[c].M == M && grouped[c].H == H && grouped[c].N == N && grouped[c].pen == pen) break;
-    if (c == grouped.size()) grouped.push_back(Class{M, H, N, pen, {}, 0});
+    if (c == grouped.size()) grouped.push_back(Class{M, H, N, pen, {}, 0, false});
     grouped[c].idx.push_back((int)i);
   }
   std::vector<Class> classes;
-  int next_lane = 0;
+  int next_big = 0;
   for (const Class& g : grouped) {
-    const size_t nf = g.idx.size();
-    if (nf >= 2) {
-      Class a = g, b = g;
-      a.idx.assign(g.idx.begin(), g.idx.begin() + nf / 2);
-      b.idx.assign(g.idx.begin() + nf / 2, g.idx.end());
-      a.lane = 0;
-      b.lane = 1;
-      classes.push_back(a);
-      classes.push_back(b);
-    } else {
+    const int nf = (int)g.idx.size();
+    bool big = true;
+    for (int i : g.idx)
+      big = big && (long long)descs[i].C * descs[i].H * descs[i].W >= kPartPxCh && descs[i].C == descs[g.idx[0]].C;
+    const int parts = big ? nf : (nf < kChains ? nf : kChains);
+    for (int k = 0; k < parts; ++k) {
       Class a = g;
-      a.lane = next_lane;
-      next_lane ^= 1;
+      a.big = big;
+      a.idx.assign(g.idx.begin() + (size_t)nf * k / parts, g.idx.begin() + (size_t)nf * (k + 1) / parts);
+      if (big) {
+        a.lane = next_big;
+        next_big = (next_big + 1) % kChains;
+      } else {
+        a.lane = k;
+      }
       classes.push_back(a);
     }
   }
@@ -950,6 +973,7 @@ int ils_smooth_batch(ils_plan* plan, const ils_frame* frames, int n) {
   struct Launch {
     Pick pk;
     int N, pen, first, lane;
+    bool big;
     WorkList row, fin, col;
   };
   std::vector<Launch> launches;
@@ -967,6 +991,7 @@ int ils_smooth_batch(ils_plan* plan, const ils_frame* frames, int n) {
     tdesc.specB = reinterpret_cast<cf*>(base + (size_t)ctot * tdesc.H * tdesc.ldS * sizeof(cf));
     L.pk = choose(plan, tdesc);
     L.lane = cl.lane;
+    L.big = cl.big;
     L.N = cl.N;
     L.pen = cl.pen;
     // the first pass reads the data term as u^0 when every frame of the class has u^0 = f
@@ -1007,25 +1032,41 @@ int ils_smooth_batch(ils_plan* plan, const ils_frame* frames, int n) {
   hipError_t e = stage_upload(plan, plan->ws, hdr.data(), hdr.size());
   if (e != hipSuccess) return record(plan, e);
 
+  // Chain `lane` on stream st: first its parts of large frames, each part's
+  // whole 2N+1-pass sequence before the next part's; then its parts of
+  // small frames in pass-major order (every part's pass k before any pass
+  // k + 1).
   int maxN = 0;
   for (const Launch& L : launches) maxN = L.N > maxN ? L.N : maxN;
-  // Pass-major order within a chain: every class's pass k is enqueued
-  // before any pass k+1.  Chain `lane` goes to st[lane].
   auto enqueue_chain = [&](int lane, hipStream_t st) -> hipError_t {
     hipError_t r = hipSuccess;
     for (const Launch& L : launches) {
-      if (L.lane != lane) continue;
+      if (L.lane != lane || !L.big) continue;
+      r = timed(plan, 0, [&] { return L.pk.rv->launch(L.first, L.pen, L.row, st); });
+      if (r != hipSuccess) return r;
+      for (int n = 0; n < L.N; ++n) {
+        r = timed(plan, 3, [&] { return L.pk.cv->launch(L.col, st); });
+        if (r != hipSuccess) return r;
+        if (n + 1 < L.N)
+          r = timed(plan, 1, [&] { return L.pk.rv->launch(ilsk::ROW_MID, L.pen, L.row, st); });
+        else
+          r = timed(plan, 2, [&] { return L.pk.rv->launch(ilsk::ROW_FINAL, L.pen, L.fin, st); });
+        if (r != hipSuccess) return r;
+      }
+    }
+    for (const Launch& L : launches) {
+      if (L.lane != lane || L.big) continue;
       r = timed(plan, 0, [&] { return L.pk.rv->launch(L.first, L.pen, L.row, st); });
       if (r != hipSuccess) return r;
     }
     for (int n = 0; n < maxN; ++n) {
       for (const Launch& L : launches) {
-        if (L.lane != lane || n >= L.N) continue;
+        if (L.lane != lane || L.big || n >= L.N) continue;
         r = timed(plan, 3, [&] { return L.pk.cv->launch(L.col, st); });
         if (r != hipSuccess) return r;
       }
       for (const Launch& L : launches) {
-        if (L.lane != lane || n >= L.N) continue;
+        if (L.lane != lane || L.big || n >= L.N) continue;
         if (n + 1 < L.N)
           r = timed(plan, 1, [&] { return L.pk.rv->launch(ilsk::ROW_MID, L.pen, L.row, st); });
         else
@@ -1035,11 +1076,10 @@ int ils_smooth_batch(ils_plan* plan, const ils_frame* frames, int n) {
     }
     return r;
   };
-  bool two = false;
-  for (const Launch& L : launches) two = two || L.lane == 1;
-  if (plan->prof_on || !plan->cap_stream) {  // both chains in order on the caller's stream
-    e = enqueue_chain(0, plan->stream);
-    if (e == hipSuccess) e = enqueue_chain(1, plan->stream);
+  bool used[kChains] = {};
+  for (const Launch& L : launches) used[L.lane] = true;
+  if (plan->prof_on || !plan->cap_stream) {  // the chains one after another on the caller's stream
+    for (int c = 0; c < kChains && e == hipSuccess; ++c) e = enqueue_chain(c, plan->stream);
     return record(plan, e);
   }
 
@@ -1069,18 +1109,17 @@ int ils_smooth_batch(ils_plan* plan, const ils_frame* frames, int n) {
     hipGraph_t g = nullptr;
     e = hipStreamBeginCapture(plan->cap_stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return record(plan, e);
-    // chain 1 forks from the start of the capture and joins before its end,
-    // so the graph holds the two chains as independent branches
-    hipError_t el = hipSuccess;
-    if (two) {
-      el = hipEventRecord(plan->fork_ev, plan->cap_stream);
-      if (el == hipSuccess) el = hipStreamWaitEvent(plan->cap_stream2, plan->fork_ev, 0);
-    }
-    if (el == hipSuccess) el = enqueue_chain(0, plan->cap_stream);
-    if (two) {
-      if (el == hipSuccess) el = enqueue_chain(1, plan->cap_stream2);
-      if (el == hipSuccess) el = hipEventRecord(plan->join_ev, plan->cap_stream2);
-      if (el == hipSuccess) el = hipStreamWaitEvent(plan->cap_stream, plan->join_ev, 0);
+    // chains 1.. fork from the start of the capture and join before its
+    // end, so the graph holds the chains as independent branches
+    hipError_t el = hipEventRecord(plan->fork_ev, plan->cap_stream);
+    for (int c = 1; c < kChains && el == hipSuccess; ++c)
+      if (used[c]) el = hipStreamWaitEvent(plan->chain_stream[c], plan->fork_ev, 0);
+    for (int c = 0; c < kChains && el == hipSuccess; ++c)
+      if (used[c]) el = enqueue_chain(c, plan->chain_stream[c]);
+    for (int c = 1; c < kChains && el == hipSuccess; ++c) {
+      if (!used[c]) continue;
+      el = hipEventRecord(plan->join_ev[c], plan->chain_stream[c]);
+      if (el == hipSuccess) el = hipStreamWaitEvent(plan->cap_stream, plan->join_ev[c], 0);
     }
     e = hipStreamEndCapture(plan->cap_stream, &g);
     if (el != hipSuccess) e = el;
