@@ -1090,6 +1090,7 @@ int ils_smooth_batch(ils_plan* plan, const ils_frame* frames, int n) {
   sig.push_back((long long)hdr.size());
   for (const Launch& L : launches) {
     sig.push_back(L.lane);
+    sig.push_back(L.big);
     sig.push_back((long long)(uintptr_t)L.pk.rv);
     sig.push_back((long long)(uintptr_t)L.pk.cv);
     sig.push_back(L.N);
