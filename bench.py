@@ -170,6 +170,20 @@ def surrogate_gain(ring, H, W, weights, say):
         "weights_step": int(z["step"]),
     }
     res["gain_vs_plain_N4"] = round(res["plain"]["N4"]["ms_per_frame"] / res["surrogate"]["gated_ms_per_frame"], 3)
+    # like for like with batches: plain N = 4 as one 16-frame batched call
+    # against gated inference whose T(v) and fallback are batched calls too
+    say("surrogate: batched plain ILS and batched gated inference")
+    plan_b = ils.Plan(H, W, 3, max_frames=B)
+    outs_b = [torch.empty_like(ring[0]) for _ in range(B)]
+    frames_b = [(f[b], float(lam[b]), float(p[b]), 1e-4, 4) for b in range(B)]
+    tpb, _ = timed(lambda: plan_b.smooth_batch(frames_b, outs=outs_b))
+    tgb, (out_b, _, fb_b) = timed(lambda: net.infer_gated(plan_b, f, lam, p, 1e-4, 4, tau), reps=2)
+    torch.cuda.synchronize()
+    if not torch.equal(out_b, out) or list(fb_b) != list(fb):
+        raise RuntimeError("batched gated inference differs from the per-image one")
+    res["batched"] = {"plain_N4_ms_per_frame": round(tpb * 1e3 / B, 4), "gated_ms_per_frame": round(tgb * 1e3 / B, 4),
+                      "gain_vs_plain_N4": round(tpb / tgb, 3)}
+    plan_b.close()
     net.close()
     plan.close()
     return res

@@ -189,11 +189,17 @@ int ils_iterate_from_c(ils_plan* plan, const float* f, const float* u0, int H, i
                        float p, float eps, float c, int N, float* out);
 
 /* Smooth n frames of possibly different sizes and parameters in one
- * enqueue: one launch per pass and size class over all its frames, the
- * whole sequence replayed as one HIP graph (unless ILS_PLAN_NO_GRAPH or
- * pass timing is active).  frames is a host array,
- * read during the call.  Each frame obeys the rules of ils_smooth.  The
- * workspace must hold ils_batch_workspace_bytes(frames, n). */
+ * enqueue: frames of equal size, N and penalty form a class, run with one
+ * launch per pass over a part of the class (one part per frame for frames
+ * of one channel count with at least 4 Mi pixel-channels each, else two
+ * parts); the parts form two independent chains of passes, the whole
+ * sequence replayed as one HIP graph (unless ILS_PLAN_NO_GRAPH or pass
+ * timing is active).  Results are bitwise those of one ils_smooth (or
+ * ils_iterate_from, when u0 is set) per frame.  frames is a host array,
+ * read during the call.  Each frame obeys the rules of ils_smooth.  Returns
+ * ILS_ERR_INVALID_ARG for n above the plan's max_frames and
+ * ILS_ERR_WORKSPACE when the workspace holds less than
+ * ils_batch_workspace_bytes(frames, n), before anything is enqueued. */
 int ils_smooth_batch(ils_plan* plan, const ils_frame* frames, int n);
 
 /* Per-frame root-mean-square difference: rms[i] = sqrt(mean((a_i - b_i)^2))

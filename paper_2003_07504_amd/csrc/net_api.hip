@@ -604,13 +604,26 @@ int ils_surrogate_infer(ils_net* n, ils_plan* plan, const float* f, const float*
   const size_t img = (size_t)3 * H * W;
   std::vector<const float*> pa(B), pb(B);
   std::vector<long long> cnt(B, (long long)img);
+  // T(v) for every image: one batched call when the plan holds B frames of
+  // this size (every argument was checked above, so a refusal can only be
+  // the plan's frame count or workspace), else image by image; both give
+  // the same bits.
+  std::vector<ils_frame> tv(B);
   for (int b = 0; b < B; ++b) {
-    rc = ils_iterate_from(plan, f + b * img, out + b * img, H, W, 3, lam_host[b], p_host[b], eps, 1,
-                          tv_scratch + b * img);
-    if (rc != ILS_OK) return rc;
+    tv[b] = ils_frame{f + b * img, tv_scratch + b * img, H, W, 3, lam_host[b], p_host[b], eps, 1, out + b * img,
+                      ILS_PENALTY_CHARBONNIER, 0.0f};
     pa[b] = tv_scratch + b * img;
     pb[b] = out + b * img;
   }
+  rc = ils_smooth_batch(plan, tv.data(), B);
+  if (rc == ILS_ERR_WORKSPACE || rc == ILS_ERR_INVALID_ARG) {
+    for (int b = 0; b < B; ++b) {
+      rc = ils_iterate_from(plan, f + b * img, out + b * img, H, W, 3, lam_host[b], p_host[b], eps, 1,
+                            tv_scratch + b * img);
+      if (rc != ILS_OK) return rc;
+    }
+  }
+  if (rc != ILS_OK) return rc;
   // per-image residuals go to the loss-partial area of the network workspace
   float* rms_dev = reinterpret_cast<float*>(n->lpart);
   rc = ils_rms_diff(plan, pa.data(), pb.data(), cnt.data(), B, rms_dev);
@@ -618,14 +631,24 @@ int ils_surrogate_infer(ils_net* n, ils_plan* plan, const float* f, const float*
   e = hipMemcpyAsync(residual_host, rms_dev, B * sizeof(float), hipMemcpyDeviceToHost, n->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(n->stream);
   if (e != hipSuccess) return rec(n, e);
+  std::vector<ils_frame> fb;
   for (int b = 0; b < B; ++b) {
     fallback_host[b] = !(residual_host[b] <= tau);  // NaN residual also falls back
-    if (fallback_host[b]) {
-      rc = ils_smooth(plan, f + b * img, H, W, 3, lam_host[b], p_host[b], eps, N, out + b * img);
+    if (fallback_host[b])
+      fb.push_back(ils_frame{f + b * img, out + b * img, H, W, 3, lam_host[b], p_host[b], eps, N, nullptr,
+                             ILS_PENALTY_CHARBONNIER, 0.0f});
+  }
+  if (fb.empty()) return ILS_OK;
+  // plain ILS for the images that fall back, batched like T(v) when the plan allows
+  rc = ils_smooth_batch(plan, fb.data(), (int)fb.size());
+  if (rc == ILS_ERR_WORKSPACE || rc == ILS_ERR_INVALID_ARG) {
+    for (const ils_frame& fr : fb) {
+      rc = ils_smooth(plan, fr.f, H, W, 3, fr.lambda, fr.p, eps, N, fr.out);
       if (rc != ILS_OK) return rc;
     }
+    rc = ILS_OK;
   }
-  return ILS_OK;
+  return rc;
 }
 
 }  // extern "C"

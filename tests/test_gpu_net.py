@@ -182,15 +182,17 @@ def test_checkpoint_round_trip(torch, S, tmp_path):
     net2.close()
 
 
-def test_gate_tau_extremes(torch, S):
+# max_frames = 1: T(v) and the fallback image by image; 2: as batched calls
+@pytest.mark.parametrize("max_frames", [1, 2])
+def test_gate_tau_extremes(torch, S, max_frames):
     """tau = 0: every image falls back and equals plain ILS bitwise;
     tau huge: none falls back and the output is the network's."""
-    _say("gate tau extremes")
+    _say(f"gate tau extremes, plan of {max_frames} frame(s)")
     from paper_2003_07504_amd import ils
     B, H, W = 2, 32, 64
     f, lam, p = _batch(B, H, W, seed=13)
     ft = torch.from_numpy(f).cuda()
-    plan = ils.Plan(H, W, 3)
+    plan = ils.Plan(H, W, 3, max_frames=max_frames)
     net = S.Net(B, H, W, seed=1)
     out0, r0, fb0 = net.infer_gated(plan, ft, lam, p, 1e-4, 4, 0.0)
     torch.cuda.synchronize()
