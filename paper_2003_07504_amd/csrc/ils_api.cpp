@@ -1078,7 +1078,10 @@ int ils_smooth_batch(ils_plan* plan, const ils_frame* frames, int n) {
   };
   bool used[kChains] = {};
   for (const Launch& L : launches) used[L.lane] = true;
-  if (plan->prof_on || !plan->cap_stream) {  // the chains one after another on the caller's stream
+  // Without a graph (pass timing, ILS_PLAN_NO_GRAPH, or a batch of one part,
+  // which has no second chain and only 2N + 1 launches): the chains one
+  // after another on the caller's stream.
+  if (plan->prof_on || !plan->cap_stream || launches.size() == 1) {
     for (int c = 0; c < kChains && e == hipSuccess; ++c) e = enqueue_chain(c, plan->stream);
     return record(plan, e);
   }
