@@ -48,7 +48,7 @@ __all__ = [
     "transfer_functions", "fft_solve", "ils", "ils_channels", "energy",
     "dense_ls_step", "fixed_point_residual", "phi_welsch", "dphi_welsch",
     "welsch_c0", "mu_update_welsch", "ils_welsch", "energy_welsch",
-    "luma", "ils_luminance", "detail_enhance", "tone_map",
+    "luma", "ils_luminance", "detail_enhance", "tone_map", "tone_map_multiscale",
 ]
 
 
@@ -356,4 +356,34 @@ def tone_map(f, lam, p, eps=1e-4, N=4, contrast=100.0, detail=1.0, workers=None)
     bmax, bmin = float(B.max()), float(B.min())
     s = np.log(contrast) / (bmax - bmin) if bmax > bmin else 1.0
     Lout = (B - bmax) * s + detail * (L - B)
+    return f * (np.exp(Lout) / y)[None]
+
+
+def tone_map_multiscale(f, lams=(0.125, 1.0, 8.0), p=1.0, eps=1e-4, N=4, contrast=100.0,
+                        weights=(1.0, 1.0, 1.0), workers=None):
+    """Multi-scale HDR tone mapping on the logarithm of the luminance
+    (Sec. 4.2, the multi-scale figure: p = 1 with lambda = 1/8, 1, 8).
+
+    L = log Y is smoothed once per scale, each time from L itself with a
+    larger lambda: B_i = ILS(L, lambda_i), i = 1..K (lambda increasing).  The
+    detail layers are the differences between successive levels,
+    D_1 = L - B_1, D_i = B_{i-1} - B_i; B_K is the base.  The base is shifted
+    to maximum 0 and scaled to span log(contrast); detail layer i is kept
+    times weights[i]; colour ratios are kept as in tone_map.  With unit
+    weights and a contrast equal to the base's own range the log luminance
+    is returned unchanged up to a shift (the layers telescope)."""
+    f = np.asarray(f, dtype=np.float64)
+    if f.ndim != 3 or f.shape[0] != 3:
+        raise ValueError("tone_map_multiscale expects a (3, H, W) RGB frame")
+    if len(lams) != len(weights) or len(lams) < 1:
+        raise ValueError("one weight per scale")
+    y = np.maximum(luma(f), LUMA_FLOOR)
+    L = np.log(y)
+    levels = [L] + [ils(L, lam, p, eps, N, workers=workers) for lam in lams]
+    base = levels[-1]
+    bmax, bmin = float(base.max()), float(base.min())
+    s = np.log(contrast) / (bmax - bmin) if bmax > bmin else 1.0
+    Lout = (base - bmax) * s
+    for i, w in enumerate(weights):
+        Lout = Lout + w * (levels[i] - levels[i + 1])
     return f * (np.exp(Lout) / y)[None]

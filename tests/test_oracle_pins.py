@@ -469,3 +469,109 @@ def test_generators_are_deterministic_and_in_range():
     assert 8 <= len(np.unique(flat)) <= 12  # cells whose centre owns no pixel can vanish
     assert np.array_equal(clipart_image(32, 40, 3, seed=2), clipart_image(32, 40, 3, seed=2))
     assert np.array_equal(texture_image(32, 40, 3, seed=2), texture_image(32, 40, 3, seed=2))
+
+
+# ------------------------------------------------ fixed-point residual pins
+def test_fixed_point_residual_p2_single_modes_closed_form():
+    """p = 2 makes mu vanish (c0 = 2, Eq. (7)), so one iteration from any v
+    returns (I + lam L)^-1 f whatever v is.  For v = f made of one cosine
+    mode per channel, T(v) - v = (1/(1 + lam S) - 1) f with S the mode's
+    eigenvalue 4 sin^2(pi k / n) (closed form of the periodic Laplacian),
+    and the mean of cos^2 over whole periods is 1/2: the residual, an RMS
+    over every pixel of every channel, is sqrt(mean_c a_c^2 / 2)."""
+    H, W, lam = 12, 20, 0.7
+    y, x = np.mgrid[0:H, 0:W]
+    modes = [(0, 3), (2, 0), (5, 7)]  # (ky, kx) per channel
+    f = np.stack([np.cos(2 * np.pi * (ky * y / H + kx * x / W)) for ky, kx in modes])
+    a = []
+    for ky, kx in modes:
+        S = 4 * np.sin(np.pi * kx / W) ** 2 + 4 * np.sin(np.pi * ky / H) ** 2
+        a.append(1.0 / (1.0 + lam * S) - 1.0)
+    expect = np.sqrt(np.mean(np.square(a)) / 2.0)
+    got = O.fixed_point_residual(f, f, lam, 2.0)
+    assert abs(got - expect) < 1e-12 * expect
+    # the exact p = 2 solve is a fixed point of T: residual 0
+    u = np.stack([f[c] * (1.0 + a[c]) for c in range(3)])
+    assert O.fixed_point_residual(u, f, lam, 2.0) < 1e-14
+
+
+def test_fixed_point_residual_2x2_by_hand():
+    """A 2 x 2 grey image at p = 2: every difference operator on a period-2
+    grid maps the pattern [[1, -1], [-1, 1]] to -2 times itself (both
+    directions), so L = D^T D has eigenvalue 4 + 4 = 8 there and 0 on the
+    constant.  f = m + d [[1, -1], [-1, 1]] gives T(v) = m + d/(1 + 8 lam)
+    pattern for any v; from v = f the residual is |d (1/(1+8 lam) - 1)|."""
+    m, d, lam = 0.3, 0.2, 0.5
+    pat = np.array([[1.0, -1.0], [-1.0, 1.0]])
+    f = m + d * pat
+    expect = abs(d * (1.0 / (1.0 + 8 * lam) - 1.0))
+    assert abs(O.fixed_point_residual(f, f, lam, 2.0) - expect) < 1e-14
+
+
+def test_fixed_point_residual_matches_dense_step():
+    """p = 0.8 on a 6 x 8 frame of two channels: T(v) taken from the dense
+    least-squares solve of Eq. (8) (no transform) gives the same residual."""
+    rng = np.random.default_rng(77)
+    f = rng.uniform(0, 1, (2, 6, 8))
+    v = f + rng.normal(0, 0.05, f.shape)
+    t = np.stack([O.dense_ls_step(v[c], f[c], 1.3, 0.8) for c in range(2)])
+    expect = float(np.sqrt(np.sum((t - v) ** 2) / t.size))
+    assert abs(O.fixed_point_residual(v, f, 1.3, 0.8) - expect) < 1e-10 * expect
+
+
+def test_luma_matches_stdlib_yiq():
+    """The Y of Python's colorsys YIQ conversion uses the BT.601 weights
+    rounded to two digits (0.30, 0.59, 0.11): a channel swap or a wrong
+    weight differs from it by far more than the rounding (<= 0.008)."""
+    import colorsys
+    rng = np.random.default_rng(5)
+    rgb = rng.uniform(0, 1, (3, 40))
+    y = O.luma(rgb[:, :, None])[:, 0]
+    ref = np.array([colorsys.rgb_to_yiq(*rgb[:, i])[0] for i in range(40)])
+    assert np.max(np.abs(y - ref)) <= 0.008 + 1e-12
+    for i, e in enumerate(np.eye(3)):  # each primary alone
+        assert abs(O.luma(e[:, None, None])[0, 0] - colorsys.rgb_to_yiq(*e)[0]) <= 0.0045
+
+
+# ---------------------------------------------- multi-scale tone mapping pins
+def test_tone_map_multiscale_layers_telescope():
+    """Unit detail weights and a contrast equal to the base's own range give
+    back the log luminance up to the shift of the base maximum: a pure
+    exposure scale f * exp(-max B_K) (the detail layers and the base sum to
+    L exactly)."""
+    from synth import hdr_image
+    f = hdr_image(16, 24, K=6, seed=4).astype(np.float64)
+    L = np.log(np.maximum(O.luma(f), O.LUMA_FLOOR))
+    lams = (0.125, 1.0, 8.0)
+    BK = O.ils(L, lams[-1], 1.0, 1e-4, 4)
+    rng = float(BK.max() - BK.min())
+    out = O.tone_map_multiscale(f, lams, 1.0, 1e-4, 4, contrast=float(np.exp(rng)), weights=(1.0, 1.0, 1.0))
+    ref = f * np.exp(-BK.max())
+    assert np.max(np.abs(out - ref) / ref) < 1e-9
+
+
+def test_tone_map_multiscale_reduces_to_single_scale():
+    """Equal scales make every detail layer but the first vanish, and one
+    scale is the single-scale operator: both equal tone_map with detail =
+    the first weight."""
+    from synth import hdr_image
+    f = hdr_image(16, 24, K=6, seed=5).astype(np.float64)
+    single = O.tone_map(f, 2.0, 1.0, 1e-4, 4, contrast=40.0, detail=1.7)
+    equal = O.tone_map_multiscale(f, (2.0, 2.0, 2.0), 1.0, 1e-4, 4, contrast=40.0, weights=(1.7, 5.0, 9.0))
+    one = O.tone_map_multiscale(f, (2.0,), 1.0, 1e-4, 4, contrast=40.0, weights=(1.7,))
+    assert np.max(np.abs(equal - single) / single) < 1e-12
+    assert np.max(np.abs(one - single) / single) < 1e-12
+
+
+def test_tone_map_multiscale_keeps_colour_ratios_and_base_range():
+    from synth import hdr_image
+    f = hdr_image(16, 24, K=6, seed=6).astype(np.float64)
+    lams, w = (0.125, 1.0, 8.0), (1.2, 1.5, 2.0)
+    out = O.tone_map_multiscale(f, lams, 1.0, 1e-4, 4, contrast=60.0, weights=w)
+    ratio = out / f
+    assert np.max(np.abs(ratio - ratio[0:1])) < 1e-12 * np.max(np.abs(ratio))
+    L = np.log(np.maximum(O.luma(f), O.LUMA_FLOOR))
+    lv = [L] + [O.ils(L, lam, 1.0, 1e-4, 4) for lam in lams]
+    lo = np.log(O.luma(out))
+    base_out = lo - sum(w[i] * (lv[i] - lv[i + 1]) for i in range(3))
+    assert abs(base_out.max()) < 1e-9 and abs((base_out.max() - base_out.min()) - np.log(60.0)) < 1e-9
