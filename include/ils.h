@@ -52,7 +52,7 @@ extern "C" {
 typedef struct ils_plan ils_plan;
 
 /* Penalty functions of the smoothness term. */
-#define ILS_PENALTY_CHARBONNIER 0 /* generalised Charbonnier phi_p, Eq. (5)    */
+#define ILS_PENALTY_CHARBONNIER 0 /* generalised Charbonnier phi_p, Eq. (2)    */
 #define ILS_PENALTY_WELSCH 1      /* Welsch phi_W, Eq. (18), c = 2 (Eq. (20))  */
 
 /* One frame of a batched call.  f / out: device pointers, C x H x W float32.
@@ -161,6 +161,23 @@ int ils_smooth_luminance(ils_plan* plan, const float* f, int H, int W, float lam
 int ils_tone_map(ils_plan* plan, const float* f, int H, int W, float lambda, float p, float eps, int N,
                  float contrast, float detail, float* out);
 
+/* Multi-scale HDR tone mapping (Sec. 4.2, the multi-scale figure: p = 1,
+ * lambda = 1/8, 1, 8).  L = log max(Y, 1e-6) as in ils_tone_map; K levels
+ * B_k = u^N of Algorithm 1 on L with lambda = lambdas[k], each smoothed from
+ * L itself (host array, increasing lambda expected but not required);
+ * detail layers D_1 = L - B_1 and D_k = B_(k-1) - B_k; base B_K compressed
+ * as in ils_tone_map (shifted to maximum 0, scaled to span log(contrast));
+ * L' = compressed base + sum_k weights[k] D_k; out_c = f_c exp(L' - L).
+ * With unit weights and the base's own range as contrast the log luminance
+ * is kept up to a shift.  1 <= K <= ILS_MAX_SCALES; weights (host array)
+ * finite and >= 0; contrast > 1.  The workspace must hold
+ * ils_tone_map_multiscale_workspace_bytes(H, W, K) (the spectra of one
+ * channel and K + 1 luminance planes).  out == f allowed. */
+#define ILS_MAX_SCALES 4
+size_t ils_tone_map_multiscale_workspace_bytes(int max_H, int max_W, int K);
+int ils_tone_map_multiscale(ils_plan* plan, const float* f, int H, int W, const float* lambdas,
+                            const float* weights, int K, float p, float eps, int N, float contrast, float* out);
+
 /* Energy of Eq. (1), E(u) = sum (u - f)^2 + lambda sum (phi(D_x u) +
  * phi(D_y u)) over all pixels and channels, periodic differences, computed
  * in double: phi = (x^2 + eps)^(p/2) (Eq. (2)) for ils_energy, the Welsch
@@ -180,7 +197,7 @@ int ils_energy_welsch(ils_plan* plan, const float* f, const float* u, int H, int
 int ils_iterate_from(ils_plan* plan, const float* f, const float* u0, int H, int W, int C,
                      float lambda, float p, float eps, int N, float* out);
 
-/* As ils_iterate_from with the constant c of Eq. (5) given explicitly
+/* As ils_iterate_from with the constant c of Eqs. (3) and (11) given explicitly
  * instead of c = c0 = p eps^(p/2 - 1) (Sec. 3.3.3: any c >= c0 keeps the
  * energy decreasing; smaller c converges faster).  c < c0 (beyond a relative
  * 1e-6) is ILS_ERR_INVALID_ARG; c within a relative 1e-6 of c0 runs the

@@ -78,7 +78,9 @@ int ils_net_destroy(ils_net* net);
  *   fallback_host: int[B] (1 where plain ILS was used).
  *   tau must be finite (ILS_ERR_NOT_CALIBRATED otherwise).  T(v) and the
  *   fallback run as batched calls when the plan holds B frames of this size
- *   (else image by image, with the same result). */
+ *   (else image by image, with the same result).  The plan enqueues on the
+ *   network's stream during the call; its own stream is restored before
+ *   the call returns. */
 int ils_surrogate_infer(ils_net* net, ils_plan* plan, const float* f, const float* lam_dev, const float* p_dev,
                         const float* lam_host, const float* p_host, float eps, int N, int B, int H, int W,
                         float tau, float* out, float* tv_scratch, float* residual_host, int* fallback_host);

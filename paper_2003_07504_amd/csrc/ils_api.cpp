@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <algorithm>
 #include <functional>
 #include <map>
 #include <string>
@@ -68,6 +69,7 @@ constexpr int kChains = 2;  // independent chains of passes in a batch graph
 // in a batch each is a part of its own (see ils_smooth_batch).
 constexpr long long kPartPxCh = 1LL << 22;
 constexpr int kMaxBatchFrames = 4096;
+constexpr size_t kGraphCache = 4;  // batch graphs kept per plan
 
 }  // namespace
 
@@ -102,8 +104,13 @@ struct ils_plan {
   hipStream_t cap_stream;
   hipStream_t chain_stream[kChains];
   hipEvent_t fork_ev, join_ev[kChains];
-  hipGraphExec_t batch_exec;
-  std::vector<long long> batch_sig;
+  // a few graphs of recent batch structures, most recently used first
+  // (gated surrogate inference alternates two structures per call)
+  struct BatchGraph {
+    std::vector<long long> sig;
+    hipGraphExec_t exec;
+  };
+  std::vector<BatchGraph> graphs;
   // tile shapes chosen per image size (H, W, C) -> (row variant, column variant)
   std::map<long long, std::pair<int, int>> tuned;
   std::string arch;
@@ -164,7 +171,7 @@ static hipError_t timed(ils_plan* plan, int kind, F&& launch) {
 
 static void free_plan(ils_plan* plan) {
   for (hipEvent_t ev : plan->ev_pool) (void)hipEventDestroy(ev);
-  if (plan->batch_exec) (void)hipGraphExecDestroy(plan->batch_exec);
+  for (auto& g : plan->graphs) (void)hipGraphExecDestroy(g.exec);
   if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
   for (int c = 1; c < kChains; ++c) {
     if (plan->chain_stream[c]) (void)hipStreamDestroy(plan->chain_stream[c]);
@@ -277,6 +284,8 @@ hipError_t ilsk_launch_loglum(const float* rgb, float* L, long long plane, float
 hipError_t ilsk_launch_minmax(const float* B, long long plane, float* scratch, float* mm, hipStream_t st);
 hipError_t ilsk_launch_tonemap(const float* f, const float* L, const float* B, const float* mm, float log_contrast,
                                float detail, float* out, long long plane, hipStream_t st);
+hipError_t ilsk_launch_tonemap_ms(const float* f, const float* L, const float* const* B, const float* w, int K,
+                                  const float* mm, float log_contrast, float* out, long long plane, hipStream_t st);
 
 // ---------------------------------------------------------------- tuner
 // Lengths of 480 and more offer two row-band and two column-tile shapes.
@@ -489,7 +498,6 @@ int ils_plan_create(ils_plan** plan_out, int max_H, int max_W, int max_C, int ma
     plan->join_ev[c] = nullptr;
   }
   plan->fork_ev = nullptr;
-  plan->batch_exec = nullptr;
   for (int i = 0; i < kStageSlots; ++i) {
     plan->stage[i] = nullptr;
     plan->stage_ev[i] = nullptr;
@@ -861,6 +869,59 @@ int ils_tone_map(ils_plan* plan, const float* f, int H, int W, float lambda, flo
   return record(plan, e);
 }
 
+size_t ils_tone_map_multiscale_workspace_bytes(int max_H, int max_W, int K) {
+  if (max_H < 2 || max_W < 2 || (max_W & 1) || K < 1 || K > ILS_MAX_SCALES) return 0;
+  return kBatchHeaderBytes + frame_ws_bytes(max_H, max_W, 1) +
+         (size_t)(K + 1) * align_up((size_t)max_H * max_W * sizeof(float), 256);
+}
+
+int ils_tone_map_multiscale(ils_plan* plan, const float* f, int H, int W, const float* lambdas,
+                            const float* weights, int K, float p, float eps, int N, float contrast, float* out) {
+  if (!plan || !f || !out || !lambdas || !weights || K < 1 || K > ILS_MAX_SCALES) return ILS_ERR_INVALID_ARG;
+  if (!finite_f(contrast) || !(contrast > 1.0f)) return ILS_ERR_INVALID_ARG;
+  for (int k = 0; k < K; ++k) {
+    if (!finite_f(weights[k]) || weights[k] < 0.0f) return ILS_ERR_INVALID_ARG;
+    int rc = check_params(lambdas[k], p, eps, N);
+    if (rc != ILS_OK) return rc;
+  }
+  int rc = check_size(plan, H, W, 1);
+  if (rc != ILS_OK) return rc;
+  if (plan->ws_bytes < ils_tone_map_multiscale_workspace_bytes(H, W, K)) return ILS_ERR_WORKSPACE;
+  const long long plane = (long long)H * W;
+  const size_t plane_b = align_up((size_t)plane * sizeof(float), 256);
+  char* base = plan->ws + kBatchHeaderBytes;
+  const size_t spec = frame_ws_bytes(H, W, 1);
+  float* L = reinterpret_cast<float*>(base + spec);
+  const float* B[ILS_MAX_SCALES];
+  float* scratch = reinterpret_cast<float*>(plan->ws);  // header: min/max partials, then the pair
+  float* mm = scratch + 2 * 256;
+  hipError_t e = ilsk_launch_loglum(f, L, plane, 1e-6f, plan->stream);
+  if (e != hipSuccess) return record(plan, e);
+  // every level is smoothed from L itself (not from the previous level)
+  for (int k = 0; k < K; ++k) {
+    float* Bk = reinterpret_cast<float*>(base + spec + (size_t)(k + 1) * plane_b);
+    B[k] = Bk;
+    if (N == 0 || lambdas[k] == 0.0f) {
+      e = hipMemcpyAsync(Bk, L, (size_t)plane * sizeof(float), hipMemcpyDeviceToDevice, plan->stream);
+      if (e != hipSuccess) return record(plan, e);
+      continue;
+    }
+    FrameDesc d;
+    fill_desc(plan, d, H, W, 1, lambdas[k], p, eps);
+    d.f = L;
+    d.u0 = L;
+    d.out = Bk;
+    d.specA = reinterpret_cast<cf*>(base);
+    d.specB = reinterpret_cast<cf*>(base + (size_t)H * d.ldS * sizeof(cf));
+    rc = run_frame(plan, d, N);
+    if (rc != ILS_OK) return rc;
+  }
+  e = ilsk_launch_minmax(B[K - 1], plane, scratch, mm, plan->stream);
+  if (e == hipSuccess)
+    e = ilsk_launch_tonemap_ms(f, L, B, weights, K, mm, (float)std::log((double)contrast), out, plane, plan->stream);
+  return record(plan, e);
+}
+
 int ils_smooth_batch(ils_plan* plan, const ils_frame* frames, int n) {
   if (!plan || !frames || n < 1) return ILS_ERR_INVALID_ARG;
   if (n > plan->max_frames || n > kMaxBatchFrames) return ILS_ERR_INVALID_ARG;
@@ -1105,11 +1166,16 @@ int ils_smooth_batch(ils_plan* plan, const ils_frame* frames, int n) {
     sig.push_back(L.col.total);
   }
   for (size_t o : offs) sig.push_back((long long)o);
-  if (!plan->batch_exec || sig != plan->batch_sig) {
-    if (plan->batch_exec) {
-      (void)hipGraphExecDestroy(plan->batch_exec);
-      plan->batch_exec = nullptr;
+  size_t hit = 0;
+  while (hit < plan->graphs.size() && plan->graphs[hit].sig != sig) ++hit;
+  if (hit < plan->graphs.size()) {
+    std::rotate(plan->graphs.begin(), plan->graphs.begin() + hit, plan->graphs.begin() + hit + 1);
+  } else {
+    if (plan->graphs.size() >= kGraphCache) {
+      (void)hipGraphExecDestroy(plan->graphs.back().exec);
+      plan->graphs.pop_back();
     }
+    hipGraphExec_t exec = nullptr;
     hipGraph_t g = nullptr;
     e = hipStreamBeginCapture(plan->cap_stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return record(plan, e);
@@ -1127,15 +1193,12 @@ int ils_smooth_batch(ils_plan* plan, const ils_frame* frames, int n) {
     }
     e = hipStreamEndCapture(plan->cap_stream, &g);
     if (el != hipSuccess) e = el;
-    if (e == hipSuccess) e = hipGraphInstantiate(&plan->batch_exec, g, nullptr, nullptr, 0);
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
     if (g) (void)hipGraphDestroy(g);
-    if (e != hipSuccess) {
-      plan->batch_exec = nullptr;
-      return record(plan, e);
-    }
-    plan->batch_sig = sig;
+    if (e != hipSuccess) return record(plan, e);
+    plan->graphs.insert(plan->graphs.begin(), ils_plan::BatchGraph{sig, exec});
   }
-  return record(plan, hipGraphLaunch(plan->batch_exec, plan->stream));
+  return record(plan, hipGraphLaunch(plan->graphs.front().exec, plan->stream));
 }
 
 // ------------------------------------------------------------ debug passes
@@ -1223,3 +1286,5 @@ int ilsk_plan_scratch(ils_plan* plan, void** scratch, size_t* bytes, void** stre
 int ilsk_plan_upload(ils_plan* plan, void* dst, const void* src, size_t bytes) {
   return record(plan, stage_upload(plan, dst, src, bytes));
 }
+
+void* ilsk_plan_stream(ils_plan* plan) { return plan ? static_cast<void*>(plan->stream) : nullptr; }

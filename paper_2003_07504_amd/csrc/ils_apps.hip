@@ -2,7 +2,8 @@
 //   * luminance-only colour mode: Y = 0.299 R + 0.587 G + 0.114 B, smooth Y,
 //     add the change of Y back to every channel (a YUV round trip with U, V
 //     unchanged);
-//   * single-scale HDR tone mapping on the logarithm of the luminance;
+//   * single- and multi-scale HDR tone mapping on the logarithm of the
+//     luminance;
 //   * the energy of Eq. (1) for the Charbonnier (Eq. (2)) and Welsch
 //     (Eq. (18)) penalties, accumulated in double, for convergence studies.
 // Elementwise kernels are grid-stride loops over the pixels of a plane.
@@ -110,6 +111,37 @@ __global__ void __launch_bounds__(kThreads) k_tonemap(const float* f, const floa
   }
 }
 
+// Multi-scale version: K smoothed levels B_1..B_K of L (increasing lambda),
+// detail layers D_1 = L - B_1, D_i = B_{i-1} - B_i kept times w_i, base B_K
+// compressed as in k_tonemap (mm = its min and max).
+constexpr int kMaxScales = 4;
+struct MultiScaleArgs {
+  const float* B[kMaxScales];
+  float w[kMaxScales];
+  int K;
+};
+__global__ void __launch_bounds__(kThreads) k_tonemap_ms(const float* f, const float* __restrict__ L, MultiScaleArgs a,
+                                                          const float* __restrict__ mm, float log_contrast, float* out,
+                                                          long long plane) {
+  const float bmin = mm[0], bmax = mm[1];
+  const float s = bmax > bmin ? log_contrast / (bmax - bmin) : 1.0f;
+  const long long stride = (long long)gridDim.x * kThreads;
+  for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < plane; i += stride) {
+    const float l = L[i];
+    float prev = l, acc = 0.0f;
+    for (int k = 0; k < a.K; ++k) {
+      const float b = a.B[k][i];
+      acc = fmaf(a.w[k], prev - b, acc);
+      prev = b;
+    }
+    const float g = expf(fmaf(prev - bmax, s, acc) - l);
+    const float r = f[i], gg = f[i + plane], bb = f[i + 2 * plane];
+    out[i] = r * g;
+    out[i + plane] = gg * g;
+    out[i + 2 * plane] = bb * g;
+  }
+}
+
 struct EnergyArgs {
   const float* f;
   const float* u;
@@ -203,6 +235,19 @@ hipError_t ilsk_launch_tonemap(const float* f, const float* L, const float* B, c
                                float detail, float* out, long long plane, hipStream_t st) {
   hipLaunchKernelGGL(k_tonemap, dim3(grid_for(plane)), dim3(kThreads), 0, st, f, L, B, mm, log_contrast, detail, out,
                      plane);
+  return hipGetLastError();
+}
+
+hipError_t ilsk_launch_tonemap_ms(const float* f, const float* L, const float* const* B, const float* w, int K,
+                                  const float* mm, float log_contrast, float* out, long long plane, hipStream_t st) {
+  if (K < 1 || K > kMaxScales) return hipErrorInvalidValue;
+  MultiScaleArgs a{};
+  for (int k = 0; k < K; ++k) {
+    a.B[k] = B[k];
+    a.w[k] = w[k];
+  }
+  a.K = K;
+  hipLaunchKernelGGL(k_tonemap_ms, dim3(grid_for(plane)), dim3(kThreads), 0, st, f, L, a, mm, log_contrast, out, plane);
   return hipGetLastError();
 }
 

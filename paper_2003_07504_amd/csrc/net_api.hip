@@ -12,6 +12,9 @@
 #include "../../include/ils_net.h"
 #include "net_kernels.hpp"
 
+// The stream a plan currently enqueues on (library-internal, ils_api.cpp).
+void* ilsk_plan_stream(ils_plan* plan);
+
 using namespace ilsn;
 
 namespace {
@@ -584,21 +587,11 @@ int ils_net_destroy(ils_net* n) {
 // Residual-gated surrogate inference.  v = net(f); for every image
 // T(v) = one ILS iteration from u^0 = v with data term f; R = rms(T(v) - v);
 // images with R > tau are recomputed with plain ILS (N iterations) into out.
-int ils_surrogate_infer(ils_net* n, ils_plan* plan, const float* f, const float* lam_dev, const float* p_dev,
-                        const float* lam_host, const float* p_host, float eps, int N, int B, int H, int W,
-                        float tau, float* out, float* tv_scratch, float* residual_host, int* fallback_host) {
-  if (!n || !plan || !f || !lam_dev || !p_dev || !lam_host || !p_host || !out || !tv_scratch || !residual_host ||
-      !fallback_host)
-    return ILS_ERR_INVALID_ARG;
-  if (!std::isfinite(tau)) return ILS_ERR_NOT_CALIBRATED;
-  int rc = check_batch(n, B, H, W);
-  if (rc != ILS_OK) return rc;
-  for (int b = 0; b < B; ++b) {
-    rc = ils_check_args(H, W, 3, lam_host[b], p_host[b], eps, N);
-    if (rc != ILS_OK) return rc;
-  }
-  rc = ils_plan_set_stream(plan, n->stream);
-  if (rc != ILS_OK) return rc;
+// The gated pipeline proper; the plan is already bound to the network's stream.
+static int surrogate_infer_bound(ils_net* n, ils_plan* plan, const float* f, const float* lam_dev, const float* p_dev,
+                                 const float* lam_host, const float* p_host, float eps, int N, int B, int H, int W,
+                                 float tau, float* out, float* tv_scratch, float* residual_host, int* fallback_host) {
+  int rc = ILS_OK;
   hipError_t e = run_forward(n, f, lam_dev, p_dev, B, H, W, out);
   if (e != hipSuccess) return rec(n, e);
   const size_t img = (size_t)3 * H * W;
@@ -648,6 +641,30 @@ int ils_surrogate_infer(ils_net* n, ils_plan* plan, const float* f, const float*
     }
     rc = ILS_OK;
   }
+  return rc;
+}
+
+int ils_surrogate_infer(ils_net* n, ils_plan* plan, const float* f, const float* lam_dev, const float* p_dev,
+                        const float* lam_host, const float* p_host, float eps, int N, int B, int H, int W,
+                        float tau, float* out, float* tv_scratch, float* residual_host, int* fallback_host) {
+  if (!n || !plan || !f || !lam_dev || !p_dev || !lam_host || !p_host || !out || !tv_scratch || !residual_host ||
+      !fallback_host)
+    return ILS_ERR_INVALID_ARG;
+  if (!std::isfinite(tau)) return ILS_ERR_NOT_CALIBRATED;
+  int rc = check_batch(n, B, H, W);
+  if (rc != ILS_OK) return rc;
+  for (int b = 0; b < B; ++b) {
+    rc = ils_check_args(H, W, 3, lam_host[b], p_host[b], eps, N);
+    if (rc != ILS_OK) return rc;
+  }
+  // the plan's own work goes on the network's stream for the call and back
+  // to the caller's stream on every return path
+  void* saved = ilsk_plan_stream(plan);
+  rc = ils_plan_set_stream(plan, n->stream);
+  if (rc != ILS_OK) return rc;
+  rc = surrogate_infer_bound(n, plan, f, lam_dev, p_dev, lam_host, p_host, eps, N, B, H, W, tau, out, tv_scratch,
+                             residual_host, fallback_host);
+  (void)ils_plan_set_stream(plan, saved);
   return rc;
 }
 

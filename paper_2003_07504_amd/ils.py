@@ -191,6 +191,36 @@ class Plan:
               "ils_tone_map")
         return out
 
+    def tone_map_multiscale(self, f: torch.Tensor, lams: Sequence[float] = (0.125, 1.0, 8.0), p: float = 1.0,
+                            eps: float = 1e-4, N: int = 4, contrast: float = 100.0,
+                            weights: Sequence[float] = (1.0, 1.0, 1.0),
+                            out: torch.Tensor | None = None) -> torch.Tensor:
+        """Multi-scale HDR tone mapping of a (3, H, W) linear RGB frame on log
+        luminance (one smoothing of log Y per lambda, detail layers between
+        successive levels kept times `weights`)."""
+        fc = _as_chw(f, "f")
+        if fc.shape[0] != 3:
+            raise ValueError("tone_map_multiscale needs a (3, H, W) RGB frame")
+        if len(lams) != len(weights):
+            raise ValueError("one weight per scale")
+        out = torch.empty_like(f) if out is None else out
+        oc = _as_chw(out, "out")
+        if oc.shape != fc.shape:
+            raise ValueError("out must have the shape of f")
+        _, H, W = fc.shape
+        K = len(lams)
+        need = int(self._lib.ils_tone_map_multiscale_workspace_bytes(H, W, K))
+        if need == 0 or need > self.workspace.numel():
+            raise ValueError(f"the plan's workspace holds {self.workspace.numel()} bytes; multi-scale tone mapping "
+                             f"of {H}x{W} with {K} scales needs {need}")
+        la = (ctypes.c_float * K)(*[float(v) for v in lams])
+        wa = (ctypes.c_float * K)(*[float(v) for v in weights])
+        self._bind_stream()
+        check(self._lib.ils_tone_map_multiscale(self._h, ctypes.c_void_p(fc.data_ptr()), H, W, la, wa, K, float(p),
+                                                float(eps), int(N), float(contrast), ctypes.c_void_p(oc.data_ptr())),
+              "ils_tone_map_multiscale")
+        return out
+
     def energy(self, f: torch.Tensor, u: torch.Tensor, lam: float, p: float | None = None, eps: float = 1e-4,
                gamma: float | None = None) -> torch.Tensor:
         """Eq. (1) energy (float64 GPU scalar tensor): Charbonnier with p, or

@@ -14,6 +14,14 @@ pytestmark = pytest.mark.gpu
 
 MAX_ABS = 1e-4
 REL_L2 = 1e-5
+# Tone mapping: out = f exp(L' - L), so an error d in the log luminance L'
+# is a relative error d of every output value.  L' sums the compressed base
+# (scale s = log(contrast) / range of the base, below 1 here) and the
+# detail layers (weights up to 1.5): about 2.5x the smoothing error of the
+# log-luminance levels, whose values span about 12 (log of radiances from
+# 1e-3 to 1e2), i.e. 12x the [0, 1] images' errors (measured 1e-6 to 4e-6
+# max-abs there), plus the float32 log and exp (a few 1e-7 of |L| ~ 7).
+TONE_REL = 2e-4
 
 
 def _say(msg):
@@ -186,7 +194,46 @@ def test_tone_map_parity(torch, ils, H, W, contrast, detail):
     assert plan.last_error() == 0
     rel = np.abs(out.cpu().numpy().astype(np.float64) - ref) / ref
     _say(f"  max rel {rel.max():.2e} mean rel {rel.mean():.2e}")
-    assert rel.max() < 2e-4, rel.max()
+    assert rel.max() < TONE_REL, rel.max()
+    plan.close()
+
+
+@pytest.mark.parametrize("H,W,lams,weights", [(64, 96, (0.125, 1.0, 8.0), (1.0, 1.0, 1.0)),
+                                              (256, 256, (0.125, 1.0, 8.0), (1.5, 1.2, 1.0)),
+                                              (1080, 1920, (0.125, 1.0, 8.0), (1.3, 1.1, 1.0)),
+                                              (90, 120, (0.5, 4.0), (2.0, 1.0))])
+def test_tone_map_multiscale_parity(torch, ils, H, W, lams, weights):
+    """Multi-scale HDR tone mapping (p = 1, the paper's lambda = 1/8, 1, 8)
+    against the oracle: relative error of every output value."""
+    from synth import hdr_image
+    _say(f"multi-scale tone map H={H} W={W} lams={lams} weights={weights}")
+    f = hdr_image(H, W, K=max(4, H * W // 5000), seed=61 + H)
+    ref = O.tone_map_multiscale(f.astype(np.float64), lams, 1.0, 1e-4, 4, contrast=100.0, weights=weights)
+    plan = ils.Plan(H, W, 3)
+    out = plan.tone_map_multiscale(torch.from_numpy(f).cuda(), lams, 1.0, 1e-4, 4, 100.0, weights)
+    torch.cuda.synchronize()
+    assert plan.last_error() == 0
+    rel = np.abs(out.cpu().numpy().astype(np.float64) - ref) / ref
+    _say(f"  max rel {rel.max():.2e} mean rel {rel.mean():.2e}")
+    assert rel.max() < TONE_REL, rel.max()
+    plan.close()
+
+
+def test_tone_map_multiscale_equal_scales_match_single_scale(torch, ils):
+    """Equal lambdas leave only the first detail layer: the multi-scale
+    operator then gives the single-scale one's bits up to the fused sum."""
+    from synth import hdr_image
+    f = torch.from_numpy(hdr_image(90, 120, K=8, seed=7)).cuda()
+    plan = ils.Plan(90, 120, 3)
+    a = plan.tone_map(f, 2.0, 1.0, 1e-4, 4, 50.0, 1.4)
+    b = plan.tone_map_multiscale(f, (2.0, 2.0), 1.0, 1e-4, 4, 50.0, (1.4, 3.0))
+    torch.cuda.synchronize()
+    rel = float(((a - b).abs() / a.abs()).max())
+    assert rel < 1e-6, rel
+    with pytest.raises(Exception):
+        plan.tone_map_multiscale(f, (1.0,) * 5, 1.0, 1e-4, 4, 50.0, (1.0,) * 5)
+    with pytest.raises(Exception):
+        plan.tone_map_multiscale(f, (1.0, 2.0), 1.0, 1e-4, 4, 50.0, (1.0, -1.0))
     plan.close()
 
 

@@ -127,10 +127,16 @@ CASES = [
     (480, 640, 3, 60, 0.05, 0.5, 0.9, 4, 16),
     (720, 1280, 1, 180, 0.05, 2.0, 0.5, 4, 17),
     (540, 720, 1, 70, 0.05, 1.0, 0.8, 5, 18),
+    # p outside the configs' [0.5, 1]: the paper's p = 0.2 (lambda = 0.5,
+    # N = 10; c0 ~ 796, kappa ~ 199) and 1 < p < 2
+    (256, 256, 1, 40, 0.05, 0.5, 0.2, 10, 21),
+    (1080, 1920, 3, 400, 0.05, 0.5, 0.2, 10, 22),
+    (256, 256, 1, 40, 0.05, 1.0, 1.5, 4, 23),
+    (1080, 1920, 3, 400, 0.05, 1.0, 1.5, 4, 24),
 ]
 
 
-@pytest.mark.parametrize("case", CASES, ids=[f"{c[0]}x{c[1]}x{c[2]}" for c in CASES])
+@pytest.mark.parametrize("case", CASES, ids=[f"{c[0]}x{c[1]}x{c[2]}_p{c[6]}" for c in CASES])
 def test_end_to_end_parity(torch, ils, case):
     H, W, C, K, sig, lam, p, N, seed = case
     _say(f"e2e H={H} W={W} C={C} lam={lam} p={p} N={N} seed={seed}")
