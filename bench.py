@@ -59,48 +59,65 @@ def profile_entry(kernel, H, W, C):
 
 
 def roofline_of(kernel, avg_us, alg_bytes, H, W, C):
-    """Roofline of the dominant kernel.  Two floors bound it: HBM bytes
-    (algorithmic bytes / 8 TB/s) and VALU issue (vector instructions the
-    kernel executes, counted by SQ_INSTS_VALU, x 64 lanes / the chip's
-    39.3 T lane-instructions per second with packed FP32 off).  `bound` is
-    the tighter of the two, i.e. the one with the larger fraction."""
-    hbm_ach = alg_bytes / (avg_us * 1e-6) / 1e9
-    hbm = {"achieved": round(hbm_ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": round(hbm_ach / HBM_PEAK_GBS, 4), "alg_bytes_per_launch": alg_bytes}
+    """Roofline of the dominant kernel against HBM: algorithmic bytes per
+    launch (20N+4 model, per pass kind) / the kernel's average launch
+    duration (events around a run of un-bracketed launches) / 8 TB/s.
+    `traffic` is the measured HBM bytes per launch (FETCH_SIZE + WRITE_SIZE,
+    scaled by a copy of known size) when the committed counter file was taken
+    on the current kernel sources, else null.  The kernel's vector issue rate
+    (SQ_INSTS_VALU x 64 lanes against 256 CUs x 64 lanes x 2.4 GHz, packed
+    FP32 off) is reported beside it as `alu`."""
+    ach = alg_bytes / (avg_us * 1e-6) / 1e9
     e = profile_entry(kernel, H, W, C)
-    traffic = e["bytes_per_launch"] if e else None
-    valu = (e or {}).get("sq", {}).get("SQ_INSTS_VALU")
-    out = {"bound": "hbm", **{k: hbm[k] for k in ("achieved", "peak", "unit", "frac")}, "traffic": traffic,
+    out = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": e["bytes_per_launch"] if e else None,
            "kernel": kernel, "avg_launch_us": avg_us, "alg_bytes_per_launch": alg_bytes}
+    valu = (e or {}).get("sq", {}).get("SQ_INSTS_VALU")
     if valu:
         lane = float(valu) * 64.0
-        ach = lane / (avg_us * 1e-6) / 1e12
-        alu = {"achieved": round(ach, 2), "peak": VALU_PEAK_TLANE, "unit": "T VALU lane-instr/s",
-               "frac": round(ach / VALU_PEAK_TLANE, 4), "valu_lane_instr_per_launch": int(lane)}
-        if alu["frac"] > hbm["frac"]:
-            out.update({"bound": "alu", **{k: alu[k] for k in ("achieved", "peak", "unit", "frac")},
-                        "valu_lane_instr_per_launch": alu["valu_lane_instr_per_launch"], "hbm": hbm})
-        else:
-            out["alu"] = alu
+        a = lane / (avg_us * 1e-6) / 1e12
+        out["alu"] = {"achieved": round(a, 2), "peak": VALU_PEAK_TLANE, "unit": "T VALU lane-instr/s",
+                      "frac": round(a / VALU_PEAK_TLANE, 4), "valu_lane_instr_per_launch": int(lane)}
     if e:
         out["traffic_read_write"] = [e.get("read_bytes"), e.get("write_bytes")]
     return out
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(frames_np, H, W, C, lam, p, eps, N, seconds):
+    """The FP64 oracle (scipy.fft) on whole frames of the workload, first with
+    all host threads (up to 16), then with one; about `seconds` each."""
     from oracle.ils import ils_channels
+
+    def leg(workers, budget):
+        t0 = time.perf_counter()
+        done = 0
+        while True:
+            ils_channels(frames_np[done % len(frames_np)].astype("float64"), lam, p, eps, N, workers=workers)
+            done += 1
+            if time.perf_counter() - t0 >= budget:
+                break
+        el = time.perf_counter() - t0
+        return done, el
+
     workers = min(16, os.cpu_count() or 1)
-    t0 = time.perf_counter()
-    done = 0
-    while True:
-        ils_channels(frames_np[done % len(frames_np)].astype("float64"), lam, p, eps, N, workers=workers)
-        done += 1
-        if time.perf_counter() - t0 >= seconds:
-            break
-    el = time.perf_counter() - t0
+    done, el = leg(workers, seconds)
+    d1, e1 = leg(1, seconds * 0.75)
     return {"value": round(done * H * W / el / 1e6, 4), "unit": "Mpixel/s", "cores": workers, "kind": "oracle",
             "sample": f"{done} frame(s) of {W}x{H}x{C}, N={N}, FP64 NumPy/SciPy oracle (scipy.fft workers={workers})",
-            "fps": round(done / el, 4)}
+            "fps": round(done / el, 4), "cpu_model": cpu_model(), "host_threads": os.cpu_count(),
+            "single_thread": {"value": round(d1 * H * W / e1 / 1e6, 4), "unit": "Mpixel/s", "cores": 1,
+                              "sample": f"{d1} frame(s), scipy.fft workers=1", "fps": round(d1 / e1, 4)}}
 
 
 def surrogate_gain(ring, H, W, weights, say):
@@ -293,6 +310,46 @@ def convergence_figures(ring, say, n_max=30):
     return res
 
 
+def convergence_sweeps(ring, say, n_max=30):
+    """Energy-decrease trends of Sec. 3.2 and Sec. 3.3.4 on one channel of a
+    1080p frame (device energy kernel, iterations one at a time): for
+    lambda in {0.1, 0.5, 1, 5, 10} x p in {0.2, 0.5, 0.8, 1} (eps = 1e-4) and
+    for eps in {1e-2, 1e-4, 1e-5} (lambda = 1, p = 0.8), the share of the
+    N = n_max energy decrease reached at N = 1, 2, 4, 6, 10, and whether the
+    energy decreased at every iteration."""
+    import torch
+
+    from paper_2003_07504_amd import ils
+
+    f = ring[0][:1].contiguous()
+    C, H, W = f.shape
+    plan = ils.Plan(H, W, C)
+
+    def curve(lam, p, eps):
+        u = f.clone()
+        nxt = torch.empty_like(f)
+        es = [plan.energy(f, u, lam, p, eps)]
+        for _ in range(n_max):
+            plan.iterate_from(f, u, lam, p, eps, 1, out=nxt)
+            u, nxt = nxt, u
+            es.append(plan.energy(f, u, lam, p, eps))
+        es = [float(e) for e in torch.stack(es).cpu()]
+        total = es[0] - es[-1]
+        share = {f"N{n}": round((es[0] - es[n]) / total, 4) if total > 0 else None for n in (1, 2, 4, 6, 10)}
+        return {"share_of_decrease": share, "monotone": all(b <= a * (1 + 1e-12) for a, b in zip(es, es[1:])),
+                "E_ratio_N30": round(es[-1] / es[0], 5)}
+
+    grid = {}
+    for lam in (0.1, 0.5, 1.0, 5.0, 10.0):
+        for p in (0.2, 0.5, 0.8, 1.0):
+            grid[f"lambda={lam},p={p}"] = curve(lam, p, 1e-4)
+    eps_sweep = {f"eps={e:g}": curve(1.0, 0.8, e) for e in (1e-2, 1e-4, 1e-5)}
+    plan.close()
+    res = {"frame": f"1920x1080, channel 0 of ring frame 0, N up to {n_max}", "lambda_x_p": grid, "eps": eps_sweep}
+    say(f"eps sweep share at N=1: { {k: v['share_of_decrease']['N1'] for k, v in eps_sweep.items()} }")
+    return res
+
+
 def batch_mix_figures(say, reps=3):
     """Uneven-size batch: 64 frames drawn from {640x480, 1280x720, 1920x1080,
     3840x2160} x {grey, RGB} with per-frame lambda ~ U[0.5, 2], p ~ U[0.5, 1],
@@ -413,7 +470,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=256)
     ap.add_argument("--warmup", type=int, default=32)
-    ap.add_argument("--ring", type=int, default=16, help="distinct frames cycled through")
+    ap.add_argument("--ring", type=int, default=32, help="distinct frames cycled through")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the hot-frame, batched and surrogate figures")
@@ -476,17 +533,43 @@ def main():
     mpx = args.steps * H * W / elapsed / 1e6
     fps = args.steps / elapsed
 
-    # ---- per-pass durations (HIP events around every launch, same workload)
-    say("per-pass event timing")
-    plan.profile_begin()
-    run(args.warmup + args.steps, args.steps)
-    prof = plan.profile_end()
+    # ---- median step time: one event before every step, >= 50 steps
+    n_med = max(64, args.steps)
+    say(f"median leg: {n_med} steps with an event before each")
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(n_med + 1)]
+    k0 = args.warmup + args.steps
+    for i in range(n_med):
+        evs[i].record()
+        run(k0 + i, 1)
+    evs[n_med].record()
     torch.cuda.synchronize()
+    step_ms = sorted(evs[i].elapsed_time(evs[i + 1]) for i in range(n_med))
+    median_ms = step_ms[n_med // 2]
+
+    # ---- per-pass durations: a run of launches of one pass kind, back to
+    # back on the plan's stream (f cycling through the ring as in the steps),
+    # with one event pair around the run: no event between launches
+    say("per-pass timing (runs of un-bracketed launches)")
     pb = pass_bytes(H, W, C)
-    per_kind = {k: {"avg_us": round(1e3 * t / n, 3), "launches": n, "alg_bytes": pb[k],
-                    "alg_GBs": round(pb[k] / (t / n * 1e-3) / 1e9, 1)}
-                for k, (t, n) in prof.items() if n > 0}
-    dom = max(per_kind, key=lambda k: per_kind[k]["avg_us"] * per_kind[k]["launches"])
+    per_step = {"row_first": 1, "row_mid": N - 1, "row_final": 1, "column": N}
+    reps = 64
+    per_kind = {}
+    for kind in ils.Plan.PASS_KINDS:
+        for i in range(4):
+            plan.enqueue_pass(kind, ring[i % len(ring)], lam, p, eps, out=outs[i % len(ring)])
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for i in range(reps):
+            plan.enqueue_pass(kind, ring[i % len(ring)], lam, p, eps, out=outs[i % len(ring)])
+        b.record()
+        torch.cuda.synchronize()
+        us = a.elapsed_time(b) * 1e3 / reps
+        per_kind[kind] = {"avg_us": round(us, 3), "launches_timed": reps, "per_step": per_step[kind],
+                          "alg_bytes": pb[kind], "alg_GBs": round(pb[kind] / (us * 1e-6) / 1e9, 1)}
+    if plan.last_error() != 0:
+        raise RuntimeError("HIP error during pass timing")
+    dom = max(per_kind, key=lambda k: per_kind[k]["avg_us"] * per_kind[k]["per_step"])
     dk = per_kind[dom]
     roofline = roofline_of(dom, dk["avg_us"], dk["alg_bytes"], H, W, C)
     step_alg = step_bytes(H, W, C, N)
@@ -536,6 +619,8 @@ def main():
         extras["batch_mix_64"] = batch_mix_figures(say)
         say("energy along the iteration (1080p RGB, N up to 30)")
         extras["convergence_1080p_rgb"] = convergence_figures(ring, say)
+        say("convergence sweeps: lambda x p grid and eps (one 1080p channel, N up to 30)")
+        extras["convergence_sweeps"] = convergence_sweeps(ring, say)
         say("256x256 grey latency figures")
         extras["small_256x256_grey_n4"] = small_image_figures(say)
         say("applications (luminance mode, detail enhancement, Welsch penalty)")
@@ -570,6 +655,9 @@ def main():
         "fps": round(fps, 1),
         "alg_GBs_whole_step": round(step_alg / (ms_per_step * 1e-3) / 1e9, 1),
         "alg_bytes_per_step": step_alg,
+        "median_ms_per_step": round(median_ms, 5),
+        "median_steps": n_med,
+        "step_ms_p10_p90": [round(step_ms[n_med // 10], 5), round(step_ms[(9 * n_med) // 10], 5)],
         "host_s": round(host_s, 6),
         "gpu_event_ms": round(gpu_ms, 4),
         "roofline": roofline,

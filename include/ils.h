@@ -25,9 +25,14 @@
  *     reported by ils_last_error() after the stream has been synchronised.
  *   - The library never prints, throws or aborts.
  *   - A plan is not thread-safe: use one plan per host thread / stream.
- *   - Supported sizes: W even, and both H and W/2 in the table of compiled
- *     transform lengths (ils_length_supported); every such length is
- *     2/3/5-smooth.  Other sizes return ILS_ERR_UNSUPPORTED_SIZE.
+ *   - Supported sizes: W even, and H and W/2 each a 2/3/5-smooth length
+ *     from 2 to 4096, or one of the lengths compiled with a fixed four-step
+ *     split (ils_length_supported).  A frame whose two lengths both have a
+ *     compiled split runs the fused passes; any other supported frame runs
+ *     runtime-length passes (mixed-radix Stockham transforms in LDS, the
+ *     stencil step and the row transforms in separate kernels: 28 instead
+ *     of 20 bytes per pixel-channel per iteration).  Other sizes return
+ *     ILS_ERR_UNSUPPORTED_SIZE.
  */
 #ifndef ILS_H_
 #define ILS_H_
@@ -41,7 +46,7 @@ extern "C" {
 /* Status codes. */
 #define ILS_OK 0
 #define ILS_ERR_INVALID_ARG -1      /* null pointer, bad range, NaN parameter   */
-#define ILS_ERR_UNSUPPORTED_SIZE -2 /* H or W/2 not a compiled length, W odd    */
+#define ILS_ERR_UNSUPPORTED_SIZE -2 /* H or W/2 not a supported length, W odd   */
 #define ILS_ERR_WORKSPACE -3        /* workspace missing or too small           */
 #define ILS_ERR_HIP -4              /* a HIP call failed (see ils_last_error)    */
 #define ILS_ERR_NOT_CALIBRATED -5   /* surrogate gate used without a threshold  */
@@ -74,10 +79,11 @@ typedef struct ils_frame {
 /* Human-readable name of a status code (static string). */
 const char* ils_status_string(int status);
 
-/* 1 if L is a compiled transform length (usable as H or as W/2), else 0. */
+/* 1 if L is a supported transform length (usable as H or as W/2): a
+ * compiled length, or any 2/3/5-smooth L with 2 <= L <= 4096; else 0. */
 int ils_length_supported(int L);
 
-/* 1 if an H x W image is supported (W even, H and W/2 compiled), else 0. */
+/* 1 if an H x W image is supported (W even, H and W/2 supported), else 0. */
 int ils_size_supported(int H, int W);
 
 /* Validation of ils_smooth's size and parameter arguments without a plan
@@ -109,6 +115,27 @@ size_t ils_batch_workspace_bytes(const ils_frame* frames, int n);
  * Returns ILS_OK and sets *plan, or an error with *plan = NULL. */
 int ils_plan_create(ils_plan** plan, int max_H, int max_W, int max_C, int max_frames,
                     void* workspace, size_t ws_bytes, void* hip_stream, unsigned flags);
+
+/* Persistent single-launch sequences (SWITCHED OFF in this build).  The
+ * design: for the sizes compiled with one (256 x 256, 640 x 480,
+ * 1280 x 720, 1920 x 1080, 3840 x 2160), ils_smooth and the batched calls
+ * would run the 2N + 1 passes of a frame (or of a part of a batch) in one
+ * launch of a persistent grid: work items (row bands and column tiles, pass
+ * by pass) taken from one queue, an item of a channel's pass waiting until
+ * that channel's previous pass has completed, with results bitwise those of
+ * the per-pass launches.  Its first launches on the MI355X did not end
+ * (twice: once with waits bounded by a poll count, once with waits bounded
+ * by the real-time clock), for a reason not found yet, so the path is off:
+ * on = 0 is accepted (one launch per pass, the only mode), on = 1 returns
+ * ILS_ERR_INVALID_ARG. */
+int ils_plan_set_persistent(ils_plan* plan, int on);
+
+/* Time a wait of a persistent launch may take before it gives up, in
+ * microseconds (> 0), or the default (0: 20 ms).  For tests of the give-up
+ * path: a limit of 1 us makes later items run before the items they depend
+ * on have finished; the kernel still ends and ils_last_error then reports
+ * ILS_ERR_HIP. */
+int ils_plan_set_wait_limit(ils_plan* plan, long long microseconds);
 
 /* Change the stream later work is enqueued on. */
 int ils_plan_set_stream(ils_plan* plan, void* hip_stream);
@@ -235,6 +262,18 @@ int ils_rms_diff(ils_plan* plan, const float* const* a, const float* const* b,
 int ils_profile_begin(ils_plan* plan);
 int ils_profile_end(ils_plan* plan, double* total_ms, int* count);
 
+/* Enqueue ONE launch of one pass kind of the sequence ils_smooth runs for
+ * this frame (kind 0 = first row pass with u^0 = f, 1 = middle row pass,
+ * 2 = final row pass, 3 = column pass; Alg. 1 with the solve of Eq. (9)),
+ * with the frame's tuned tile shapes, on the plan's workspace spectra: the
+ * row passes read the second half spectrum (and f), the column pass reads
+ * the first; the final pass writes out (C x H x W, device).  The spectra's
+ * contents are left meaningless.  For timing a pass on its own with events
+ * around a run of calls (no bracketing of each launch); other rules as
+ * ils_smooth. */
+int ils_enqueue_pass(ils_plan* plan, int kind, const float* f, float* out, int H, int W, int C, float lambda,
+                     float p, float eps);
+
 /* Last asynchronous HIP error seen by the plan (ILS_OK if none); clears it. */
 int ils_last_error(ils_plan* plan);
 
@@ -253,7 +292,8 @@ int ils_last_error(ils_plan* plan);
  * appends new ones.
  *
  * ils_shape_variants: number of row / column shapes for a supported size
- *   (1 to 6 and 1 to 4).  ILS_ERR_UNSUPPORTED_SIZE otherwise.
+ *   (1 to 6 and 1 to 4; 1 and 1 for a frame on the runtime-length passes).
+ *   ILS_ERR_UNSUPPORTED_SIZE otherwise.
  * ils_plan_tune: tune the size now if it is not yet (synchronises the
  *   plan's stream) and return the chosen shape indices (0 = default).
  * ils_plan_set_shapes: fix the shapes for a size (indices below the counts

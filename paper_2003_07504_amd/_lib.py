@@ -48,6 +48,8 @@ SIGNATURES = {
                                        ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t,
                                        ctypes.c_void_p, ctypes.c_uint]),
     "ils_plan_set_stream": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "ils_plan_set_persistent": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "ils_plan_set_wait_limit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_longlong]),
     "ils_smooth": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                   ctypes.c_int, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                   ctypes.c_int, ctypes.c_void_p]),
@@ -86,6 +88,9 @@ SIGNATURES = {
     "ils_profile_begin": (ctypes.c_int, [ctypes.c_void_p]),
     "ils_profile_end": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_int)]),
+    "ils_enqueue_pass": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_float, ctypes.c_float,
+                                        ctypes.c_float]),
     "ils_last_error": (ctypes.c_int, [ctypes.c_void_p]),
     "ils_shape_variants": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                           ctypes.POINTER(ctypes.c_int)]),

@@ -26,16 +26,20 @@ DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-Wno-unused-result"] + DEVICE_FLAGS
 
 
+# Sources that define the fused ILS pass kernels (device code, launch shapes
+# and compiled lengths); the pass counters in profiles/ are valid while these
+# are unchanged.
+KERNEL_SOURCES = ("fft_reg.hpp", "ils_desc.hpp", "ils_launch.hpp", "ils_passes.hpp", "lengths.def", "ils_persist.hpp",
+                  "persist.def")
+
+
 def source_hash() -> str:
-    """Hash of the sources of the ILS kernels and their host code (identifies
-    the build that the pass counters were taken on).  The surrogate's net_*
-    sources build separate kernels and are left out."""
+    """Hash of the sources of the fused ILS pass kernels (identifies the
+    build that the pass counters were taken on)."""
     import hashlib
     h = hashlib.sha256()
     for name in sorted(os.listdir(CSRC)):
-        if name.startswith("net_"):
-            continue
-        if name.endswith((".hip", ".hpp", ".cpp", ".def")):
+        if name in KERNEL_SOURCES:
             with open(os.path.join(CSRC, name), "rb") as fh:
                 h.update(name.encode())
                 h.update(fh.read())
@@ -52,6 +56,16 @@ def lengths():
     return out
 
 
+def persist():
+    out = []
+    with open(os.path.join(CSRC, "persist.def")) as fh:
+        for line in fh:
+            m = re.match(r"\s*ILS_PERSIST\(([\d,\s]+)\)", line)
+            if m:
+                out.append(tuple(int(v) for v in m.group(1).split(",")))
+    return out
+
+
 def _headers_mtime():
     return max(os.path.getmtime(os.path.join(CSRC, f)) for f in os.listdir(CSRC)
                if f.endswith((".hpp", ".h", ".def")))
@@ -59,8 +73,11 @@ def _headers_mtime():
 
 def _compile(src, obj, incremental, extra=()):
     if incremental and os.path.exists(obj):
-        newest = max(os.path.getmtime(src), _headers_mtime(),
-                     os.path.getmtime(os.path.join(PKG, "..", "include", "ils.h")))
+        newest = max(os.path.getmtime(src), _headers_mtime())
+        # the per-length and persistent kernel units include no public header
+        if not os.path.basename(src).startswith(("inst_", "persist_")):
+            inc = os.path.join(PKG, "..", "include")
+            newest = max([newest] + [os.path.getmtime(os.path.join(inc, h)) for h in os.listdir(inc)])
         if os.path.getmtime(obj) >= newest:
             return obj, ""
     cmd = [HIPCC, *COMMON, *extra, "-c", src, "-o", obj]
@@ -81,6 +98,15 @@ def build(jobs: int | None = None, incremental: bool = False, verbose: bool = Fa
             with open(path, "w") as fh:
                 fh.write(text)
         srcs.append((path, os.path.join(BUILD, f"inst_{L}.o"), ()))
+    for spec in persist():
+        M, H = spec[0], spec[4]
+        path = os.path.join(BUILD, f"persist_{M}_{H}.hip")
+        text = ('#include "../csrc/ils_persist.hpp"\n'
+                f"ILS_DEFINE_PERSIST({', '.join(str(v) for v in spec)})\n")
+        if not os.path.exists(path) or open(path).read() != text:
+            with open(path, "w") as fh:
+                fh.write(text)
+        srcs.append((path, os.path.join(BUILD, f"persist_{M}_{H}.o"), ()))
     srcs.append((os.path.join(CSRC, "ils_api.cpp"), os.path.join(BUILD, "ils_api.o"), ("-x", "hip")))
     for name in sorted(os.listdir(CSRC)):
         if name.endswith(".hip"):

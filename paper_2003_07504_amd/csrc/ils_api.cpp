@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "../../include/ils.h"
+#include "ils_persist.hpp"
 #include "ils_launch.hpp"
 
 using ilsk::WorkList;
@@ -30,8 +31,17 @@ using ilsk::RowVariant;
 #define ILS_LEN(L, P, Q) const LenOps* ilsk_ops_##L();
 #include "lengths.def"
 #undef ILS_LEN
+#define ILS_PERSIST(M, Pr, Qr, G, H, Pc, Qc, S) const ilsk::PersistOps* ilsk_persist_##M##_##H();
+#include "persist.def"
+#undef ILS_PERSIST
+
+// Runtime-length passes (ils_generic.hip) for 2/3/5-smooth lengths up to
+// kMaxGenericLen without a compiled split.
+const LenOps* ilsk_generic_ops(int H);
 
 namespace {
+
+constexpr int kMaxGenericLen = 4096;
 
 typedef const LenOps* (*OpsFn)();
 const OpsFn kOps[] = {
@@ -52,7 +62,35 @@ const LenOps* find_ops(int L) {
   return nullptr;
 }
 
+typedef const ilsk::PersistOps* (*PersistFn)();
+const PersistFn kPersist[] = {
+#define ILS_PERSIST(M, Pr, Qr, G, H, Pc, Qc, S) &ilsk_persist_##M##_##H,
+#include "persist.def"
+#undef ILS_PERSIST
+};
+
+// The persistent single-launch sequence for row length M and column length H, if
+// one is compiled.
+const ilsk::PersistOps* find_persist(int M, int H) {
+  for (PersistFn fn : kPersist) {
+    const ilsk::PersistOps* o = fn();
+    if (o->M == M && o->H == H) return o;
+  }
+  return nullptr;
+}
+
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+bool smooth235(int n) {
+  if (n < 1) return false;
+  while (n % 2 == 0) n /= 2;
+  while (n % 3 == 0) n /= 3;
+  while (n % 5 == 0) n /= 5;
+  return n == 1;
+}
+
+// Lengths the runtime-length passes serve (no compiled split).
+bool generic_length(int L) { return L >= 2 && L <= kMaxGenericLen && smooth235(L) && !find_ops(L); }
 
 // Padded spectrum row length (complex elements): W/2+1 rounded up to 16
 // (128-byte rows).
@@ -62,8 +100,17 @@ inline size_t frame_ws_bytes(int H, int W, int C) {
   return align_up(2ull * (size_t)C * (size_t)H * (size_t)spec_ld(W) * sizeof(cf), 256);
 }
 
-// Device-resident header of the batch work lists (descriptors + starts).
+// Device-resident header of the workspace: batch work lists (descriptors and
+// starts) from its start, the control blocks of persistent launches in its last
+// kPersistCtlBytes, whose last 256 bytes hold the wait-expiry word.
 constexpr size_t kBatchHeaderBytes = 1 << 20;
+constexpr size_t kPersistCtlBytes = 256 << 10;
+constexpr size_t kBatchListBytes = kBatchHeaderBytes - kPersistCtlBytes;
+constexpr size_t kPersistErrOff = kBatchHeaderBytes - 256;
+constexpr size_t kPersistCtlInts = (kPersistCtlBytes - 256) / sizeof(int);
+// Time a wait of a persistent launch may take before it gives up, in ticks
+// of the 100 MHz real-time clock: 20 ms.
+constexpr long long kPersistWaitTicks = 2000000;
 constexpr int kChains = 2;  // independent chains of passes in a batch graph
 // Frames of at least this many pixel-channels fill the chip on their own:
 // in a batch each is a part of its own (see ils_smooth_batch).
@@ -116,6 +163,11 @@ struct ils_plan {
   std::string arch;
   // pass timing
   bool prof_on;
+  // persistent single-launch sequences (sizes of persist.def) on, and the device's
+  // compute-unit count (grid of a persistent launch)
+  bool persist_on;
+  int cus;
+  long long wait_ticks;
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used;
   std::vector<int> prof_kind;  // kind of launch i; events 2i, 2i+1
@@ -219,19 +271,19 @@ static int check_size(const ils_plan* plan, int H, int W, int C) {
 
 // Fill a descriptor for one frame; the caller sets f/u0/out and the
 // spectrum pointers.
-static void fill_desc(const ils_plan* plan, FrameDesc& d, int H, int W, int C, float lambda,
-                      float p, float eps) {
+static void fill_desc_on(const char* tables, const std::map<int, LenTables>& tab, FrameDesc& d, int H, int W,
+                         int C, float lambda, float p, float eps) {
   const double c0 = (double)p * std::pow((double)eps, (double)p / 2.0 - 1.0);  // Eq. (11)
   const int M = W / 2;
-  const LenTables& tr = plan->tab.at(M);
-  const LenTables& tc = plan->tab.at(H);
-  d.tw_row = reinterpret_cast<const cf*>(plan->tables + tr.tw);
-  d.tw2_row = reinterpret_cast<const cf*>(plan->tables + tr.tw2);
-  d.twm_row = reinterpret_cast<const cf*>(plan->tables + tr.twm);
-  d.sx = reinterpret_cast<const float*>(plan->tables + tr.sx);
-  d.tw_col = reinterpret_cast<const cf*>(plan->tables + tc.tw);
-  d.twm_col = reinterpret_cast<const cf*>(plan->tables + tc.twm);
-  d.sy = reinterpret_cast<const float*>(plan->tables + tc.sy);
+  const LenTables& tr = tab.at(M);
+  const LenTables& tc = tab.at(H);
+  d.tw_row = reinterpret_cast<const cf*>(tables + tr.tw);
+  d.tw2_row = reinterpret_cast<const cf*>(tables + tr.tw2);
+  d.twm_row = reinterpret_cast<const cf*>(tables + tr.twm);
+  d.sx = reinterpret_cast<const float*>(tables + tr.sx);
+  d.tw_col = reinterpret_cast<const cf*>(tables + tc.tw);
+  d.twm_col = reinterpret_cast<const cf*>(tables + tc.twm);
+  d.sy = reinterpret_cast<const float*>(tables + tc.sy);
   d.H = H;
   d.W = W;
   d.C = C;
@@ -242,6 +294,9 @@ static void fill_desc(const ils_plan* plan, FrameDesc& d, int H, int W, int C, f
   d.log2_r = 0.0f;
   d.col_scale = (float)(1.0 / (2.0 * (double)H * (double)W));
   d.boost = 0.0f;
+}
+static void fill_desc(const ils_plan* plan, FrameDesc& d, int H, int W, int C, float lambda, float p, float eps) {
+  fill_desc_on(plan->tables, plan->tab, d, H, W, C, lambda, p, eps);
 }
 
 // Welsch penalty (Sec. 5): c = c0 = 2 (Eq. (20)), so kappa = lambda; the
@@ -254,6 +309,88 @@ static void fill_desc_welsch(const ils_plan* plan, FrameDesc& d, int H, int W, i
   d.a_exp = (float)(-1.4426950408889634 / (2.0 * g * g));
   d.inv_eps = 0.0f;
   d.log2_r = 0.0f;
+}
+
+// Tables of every compiled length, computed in double and rounded once to
+// float: twiddles, real-FFT factors, the |F(nabla)|^2 eigenvalues of the
+// periodic [1,-1] kernel (Eq. (9)) and the twiddle matrices of the
+// four-step split.  Offsets into `host` (256-byte aligned) go to `tab`.
+static void build_tables(std::vector<char>& host, std::map<int, LenTables>& tab) {
+  auto put = [&](size_t bytes) {
+    size_t off = align_up(host.size(), 256);
+    host.resize(off + bytes);
+    return off;
+  };
+  for (int i = 0; i < kNumLens; ++i) {
+    const int L = kLens[i];
+    LenTables t;
+    t.tw = put(sizeof(cf) * L);
+    t.tw2 = put(sizeof(cf) * (L + 1));
+    t.sx = put(sizeof(float) * (L + 1));
+    t.sy = put(sizeof(float) * L);
+    cf* tw = reinterpret_cast<cf*>(host.data() + t.tw);
+    for (int j = 0; j < L; ++j) {
+      double a = -2.0 * M_PI * (double)j / (double)L;
+      tw[j] = cf{(float)std::cos(a), (float)std::sin(a)};
+    }
+    cf* tw2 = reinterpret_cast<cf*>(host.data() + t.tw2);
+    for (int k = 0; k <= L; ++k) {
+      double a = -M_PI * (double)k / (double)L;
+      tw2[k] = cf{(float)std::cos(a), (float)std::sin(a)};
+    }
+    // |F(nabla)|^2 for the periodic [1,-1] kernel: 4 sin^2(pi k / n)
+    float* sx = reinterpret_cast<float*>(host.data() + t.sx);
+    for (int k = 0; k <= L; ++k) {
+      double s = std::sin(M_PI * (double)k / (2.0 * L));
+      sx[k] = (float)(4.0 * s * s);
+    }
+    float* sy = reinterpret_cast<float*>(host.data() + t.sy);
+    for (int l = 0; l < L; ++l) {
+      double s = std::sin(M_PI * (double)l / (double)L);
+      sy[l] = (float)(4.0 * s * s);
+    }
+    // the row transforms' twiddles as a P x (Q|1) matrix, entry [k1][t] =
+    // exp(-2 pi i t k1 / L): lanes that walk either index hit distinct banks
+    const LenOps* o = kOps[i]();
+    const int P = o->P, Q = o->Q, QP = Q | 1;
+    t.twm = put(sizeof(cf) * P * QP);
+    cf* twm = reinterpret_cast<cf*>(host.data() + t.twm);
+    tw = reinterpret_cast<cf*>(host.data() + t.tw);
+    for (int k1 = 0; k1 < P; ++k1)
+      for (int q = 0; q < QP; ++q) twm[k1 * QP + q] = q < Q ? tw[q * k1] : cf{0.0f, 0.0f};
+    tab[L] = t;
+  }
+  // lengths of the runtime-length passes: the same vectors, no matrix
+  for (int L = 2; L <= kMaxGenericLen; ++L) {
+    if (!generic_length(L)) continue;
+    LenTables t;
+    t.tw = put(sizeof(cf) * L);
+    t.tw2 = put(sizeof(cf) * (L + 1));
+    t.sx = put(sizeof(float) * (L + 1));
+    t.sy = put(sizeof(float) * L);
+    t.twm = t.tw;
+    cf* tw = reinterpret_cast<cf*>(host.data() + t.tw);
+    for (int j = 0; j < L; ++j) {
+      double a = -2.0 * M_PI * (double)j / (double)L;
+      tw[j] = cf{(float)std::cos(a), (float)std::sin(a)};
+    }
+    cf* tw2 = reinterpret_cast<cf*>(host.data() + t.tw2);
+    for (int k = 0; k <= L; ++k) {
+      double a = -M_PI * (double)k / (double)L;
+      tw2[k] = cf{(float)std::cos(a), (float)std::sin(a)};
+    }
+    float* sx = reinterpret_cast<float*>(host.data() + t.sx);
+    for (int k = 0; k <= L; ++k) {
+      double sn = std::sin(M_PI * (double)k / (2.0 * L));
+      sx[k] = (float)(4.0 * sn * sn);
+    }
+    float* sy = reinterpret_cast<float*>(host.data() + t.sy);
+    for (int l = 0; l < L; ++l) {
+      double sn = std::sin(M_PI * (double)l / (double)L);
+      sy[l] = (float)(4.0 * sn * sn);
+    }
+    tab[L] = t;
+  }
 }
 
 // Single-frame work lists for the three launch shapes of a frame.
@@ -347,7 +484,21 @@ static float time_launches(ils_plan* plan, const std::function<hipError_t()>& la
   return best;
 }
 
+// A frame with a row or column length that has no compiled split runs
+// every pass on the runtime-length kernels.
+static bool frame_generic(int H, int W) { return !find_ops(W / 2) || !find_ops(H); }
+
+// Default shapes (no tuning).
+static Pick default_pick(int H, int W) {
+  if (frame_generic(H, W)) {
+    const LenOps* g = ilsk_generic_ops(H);
+    return Pick{&g->row[0], &g->col[0]};
+  }
+  return Pick{&find_ops(W / 2)->row[0], &find_ops(H)->col[0]};
+}
+
 static Pick choose(ils_plan* plan, const FrameDesc& d) {
+  if (frame_generic(d.H, d.W)) return default_pick(d.H, d.W);
   const LenOps* orow = find_ops(d.W / 2);
   const LenOps* ocol = find_ops(d.H);
   Pick pk{&orow->row[0], &ocol->col[0]};
@@ -405,22 +556,78 @@ static Pick choose(ils_plan* plan, const FrameDesc& d) {
 
 // Enqueue Algorithm 1 for one frame (N >= 1, lambda > 0): one block per
 // work item, 2N + 1 launches.
-static int run_frame(ils_plan* plan, const FrameDesc& d, int N, int pen = ilsk::PEN_CHARBONNIER) {
-  const Pick pk = choose(plan, d);
-  hipStream_t st = plan->stream;
+// The 2N + 1 launches of one frame with the given shapes on stream st;
+// wrap(kind, launch) issues each launch (kind as in ils_profile_end).
+template <class Wrap>
+static hipError_t enqueue_frame(const Pick& pk, const FrameDesc& d, int N, int pen, hipStream_t st, Wrap&& wrap) {
   const WorkList wrow = one_frame(d, row_items(pk.rv, ilsk::ROW_MID, d));
   const WorkList wfin = one_frame(d, row_items(pk.rv, ilsk::ROW_FINAL, d));
   const WorkList wcol = one_frame(d, col_items(pk.cv, d));
   const int first = (d.f == d.u0) ? ilsk::ROW_FIRST_SAME : ilsk::ROW_FIRST;
-  hipError_t e = timed(plan, 0, [&] { return pk.rv->launch(first, pen, wrow, st); });
+  hipError_t e = wrap(0, [&] { return pk.rv->launch(first, pen, wrow, st); });
   for (int n = 0; n < N && e == hipSuccess; ++n) {
-    e = timed(plan, 3, [&] { return pk.cv->launch(wcol, st); });
+    e = wrap(3, [&] { return pk.cv->launch(wcol, st); });
     if (e != hipSuccess) break;
     if (n + 1 < N)
-      e = timed(plan, 1, [&] { return pk.rv->launch(ilsk::ROW_MID, pen, wrow, st); });
+      e = wrap(1, [&] { return pk.rv->launch(ilsk::ROW_MID, pen, wrow, st); });
     else
-      e = timed(plan, 2, [&] { return pk.rv->launch(ilsk::ROW_FINAL, pen, wfin, st); });
+      e = wrap(2, [&] { return pk.rv->launch(ilsk::ROW_FINAL, pen, wfin, st); });
   }
+  return e;
+}
+
+// The persistent single-launch sequence for frames of d's size with N iterations
+// and `channels` channels in all, or nullptr (none compiled for the size,
+// switched off, pass timing active, or its control block would not fit).
+static const ilsk::PersistOps* persist_for(const ils_plan* plan, const FrameDesc& d, int N, long long channels) {
+  if (!plan->persist_on || plan->prof_on || N < 1) return nullptr;
+  if (ilsk::kPersistCtlHead + (2LL * N + 1) * channels > (long long)kPersistCtlInts) return nullptr;
+  return find_persist(d.W / 2, d.H);
+}
+
+// Enqueue one persistent launch: frames from the device descriptor array descs
+// (channel prefix sums ch_start), or the single frame `one` when descs is
+// null; control block at ctl (ctl_ints ints) in the workspace header.
+static hipError_t enqueue_persist(ils_plan* plan, const ilsk::PersistOps* fo, const FrameDesc* descs,
+                                const int* ch_start, const FrameDesc& one, int n, int C, long long channels, int N,
+                                int pen, int first, int* ctl, hipStream_t st) {
+  if (plan->cus <= 0) {
+    hipDeviceProp_t prop;
+    hipError_t e = hipGetDeviceProperties(&prop, plan->device);
+    if (e != hipSuccess) return e;
+    plan->cus = prop.multiProcessorCount;
+  }
+  const int per_cu = fo->per_cu(pen);
+  if (per_cu <= 0) return hipErrorInvalidConfiguration;
+  ilsk::PersistList fl;
+  fl.descs = descs;
+  fl.one = one;
+  fl.ctl = ctl;
+  fl.err = reinterpret_cast<int*>(plan->ws + kPersistErrOff);
+  fl.ch_start = ch_start;
+  fl.n = n;
+  fl.C = C;
+  fl.N = N;
+  fl.first = first;
+  fl.nb_row = (one.H + fo->rows - 1) / fo->rows;
+  fl.nb_col = (one.W / 2 + 1 + fo->cols - 1) / fo->cols;
+  fl.wait_ticks = plan->wait_ticks;
+  const long long items = channels * ((N + 1LL) * fl.nb_row + (long long)N * fl.nb_col);
+  const long long grid = std::min<long long>(items, (long long)per_cu * plan->cus);
+  const int ctl_ints = (int)(ilsk::kPersistCtlHead + (2LL * N + 1) * channels);
+  return fo->launch(pen, fl, ctl_ints, (int)grid, st);
+}
+
+static int run_frame(ils_plan* plan, const FrameDesc& d, int N, int pen = ilsk::PEN_CHARBONNIER) {
+  if (const ilsk::PersistOps* fo = persist_for(plan, d, N, d.C)) {
+    const int first = (d.f == d.u0) ? ilsk::ROW_FIRST_SAME : ilsk::ROW_FIRST;
+    int* ctl = reinterpret_cast<int*>(plan->ws + kBatchListBytes);
+    return record(plan, enqueue_persist(plan, fo, nullptr, nullptr, d, 1, d.C, d.C, N, pen, first, ctl, plan->stream));
+  }
+  const Pick pk = choose(plan, d);
+  const hipError_t e = enqueue_frame(pk, d, N, pen, plan->stream, [&](int kind, auto&& launch) {
+    return timed(plan, kind, launch);
+  });
   return record(plan, e);
 }
 
@@ -439,7 +646,7 @@ const char* ils_status_string(int status) {
   }
 }
 
-int ils_length_supported(int L) { return find_ops(L) != nullptr ? 1 : 0; }
+int ils_length_supported(int L) { return (find_ops(L) != nullptr || generic_length(L)) ? 1 : 0; }
 
 int ils_size_supported(int H, int W) {
   if (H < 2 || W < 2 || (W & 1)) return 0;
@@ -491,6 +698,9 @@ int ils_plan_create(ils_plan** plan_out, int max_H, int max_W, int max_C, int ma
   plan->tables = nullptr;
   plan->stage_next = 0;
   plan->prof_on = false;
+  plan->persist_on = false;  // switched off: see ils_plan_set_persistent
+  plan->cus = 0;
+  plan->wait_ticks = kPersistWaitTicks;
   plan->ev_used = 0;
   plan->cap_stream = nullptr;
   for (int c = 0; c < kChains; ++c) {
@@ -534,59 +744,31 @@ int ils_plan_create(ils_plan** plan_out, int max_H, int max_W, int max_C, int ma
     }
   }
 
-  // Tables for every compiled length, computed in double and rounded once.
   std::vector<char> host;
-  auto put = [&](size_t bytes) {
-    size_t off = align_up(host.size(), 256);
-    host.resize(off + bytes);
-    return off;
-  };
-  for (int i = 0; i < kNumLens; ++i) {
-    const int L = kLens[i];
-    LenTables t;
-    t.tw = put(sizeof(cf) * L);
-    t.tw2 = put(sizeof(cf) * (L + 1));
-    t.sx = put(sizeof(float) * (L + 1));
-    t.sy = put(sizeof(float) * L);
-    cf* tw = reinterpret_cast<cf*>(host.data() + t.tw);
-    for (int j = 0; j < L; ++j) {
-      double a = -2.0 * M_PI * (double)j / (double)L;
-      tw[j] = cf{(float)std::cos(a), (float)std::sin(a)};
-    }
-    cf* tw2 = reinterpret_cast<cf*>(host.data() + t.tw2);
-    for (int k = 0; k <= L; ++k) {
-      double a = -M_PI * (double)k / (double)L;
-      tw2[k] = cf{(float)std::cos(a), (float)std::sin(a)};
-    }
-    // |F(nabla)|^2 for the periodic [1,-1] kernel: 4 sin^2(pi k / n)
-    float* sx = reinterpret_cast<float*>(host.data() + t.sx);
-    for (int k = 0; k <= L; ++k) {
-      double s = std::sin(M_PI * (double)k / (2.0 * L));
-      sx[k] = (float)(4.0 * s * s);
-    }
-    float* sy = reinterpret_cast<float*>(host.data() + t.sy);
-    for (int l = 0; l < L; ++l) {
-      double s = std::sin(M_PI * (double)l / (double)L);
-      sy[l] = (float)(4.0 * s * s);
-    }
-    // the row transforms' twiddles as a P x (Q|1) matrix, entry [k1][t] =
-    // exp(-2 pi i t k1 / L): lanes that walk either index hit distinct banks
-    const LenOps* o = kOps[i]();
-    const int P = o->P, Q = o->Q, QP = Q | 1;
-    t.twm = put(sizeof(cf) * P * QP);
-    cf* twm = reinterpret_cast<cf*>(host.data() + t.twm);
-    tw = reinterpret_cast<cf*>(host.data() + t.tw);
-    for (int k1 = 0; k1 < P; ++k1)
-      for (int q = 0; q < QP; ++q) twm[k1 * QP + q] = q < Q ? tw[q * k1] : cf{0.0f, 0.0f};
-    plan->tab[L] = t;
-  }
+  build_tables(host, plan->tab);
   hipError_t e = hipMalloc(&plan->tables, host.size());
   if (e == hipSuccess) e = hipMemcpy(plan->tables, host.data(), host.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(plan->ws + kPersistErrOff, 0, sizeof(int));
   if (e != hipSuccess) {
     free_plan(plan);
     return ILS_ERR_HIP;
   }
   *plan_out = plan;
+  return ILS_OK;
+}
+
+int ils_plan_set_persistent(ils_plan* plan, int on) {
+  if (!plan || (on != 0 && on != 1)) return ILS_ERR_INVALID_ARG;
+  // The persistent launch is switched off: its first launches did not end
+  // on the GPU, for a reason not found yet.  Only "off" is accepted.
+  if (on) return ILS_ERR_INVALID_ARG;
+  plan->persist_on = false;
+  return ILS_OK;
+}
+
+int ils_plan_set_wait_limit(ils_plan* plan, long long microseconds) {
+  if (!plan || microseconds < 0) return ILS_ERR_INVALID_ARG;
+  plan->wait_ticks = microseconds == 0 ? kPersistWaitTicks : microseconds * 100;
   return ILS_OK;
 }
 
@@ -636,6 +818,13 @@ int ils_last_error(ils_plan* plan) {
   if (!plan) return ILS_ERR_INVALID_ARG;
   hipError_t e = hipStreamQuery(plan->stream);
   if (e != hipSuccess && e != hipErrorNotReady) record(plan, e);
+  if (e == hipSuccess) {  // stream idle: read and clear the persistent launches' wait-expiry word
+    int word = 0;
+    if (hipMemcpy(&word, plan->ws + kPersistErrOff, sizeof(int), hipMemcpyDeviceToHost) == hipSuccess && word != 0) {
+      (void)hipMemset(plan->ws + kPersistErrOff, 0, sizeof(int));
+      if (plan->last_error == ILS_OK) plan->last_error = ILS_ERR_HIP;
+    }
+  }
   int r = plan->last_error;
   plan->last_error = ILS_OK;
   return r;
@@ -643,7 +832,11 @@ int ils_last_error(ils_plan* plan) {
 
 int ils_shape_variants(int H, int W, int* n_row, int* n_col) {
   if (!n_row || !n_col) return ILS_ERR_INVALID_ARG;
-  if (H < 2 || W < 2 || (W & 1) || !find_ops(H) || !find_ops(W / 2)) return ILS_ERR_UNSUPPORTED_SIZE;
+  if (!ils_size_supported(H, W)) return ILS_ERR_UNSUPPORTED_SIZE;
+  if (frame_generic(H, W)) {
+    *n_row = *n_col = 1;
+    return ILS_OK;
+  }
   *n_row = find_ops(W / 2)->nrow;
   *n_col = find_ops(H)->ncol;
   return ILS_OK;
@@ -661,6 +854,10 @@ int ils_plan_tune(ils_plan* plan, int H, int W, int C, int* row_shape, int* col_
   d.f = d.u0 = reinterpret_cast<const float*>(d.specB);
   d.out = reinterpret_cast<float*>(d.specB);
   const Pick pk = choose(plan, d);
+  if (frame_generic(H, W)) {
+    *row_shape = *col_shape = 0;
+    return ILS_OK;
+  }
   *row_shape = (int)(pk.rv - find_ops(W / 2)->row);
   *col_shape = (int)(pk.cv - find_ops(H)->col);
   return ILS_OK;
@@ -670,8 +867,10 @@ int ils_plan_set_shapes(ils_plan* plan, int H, int W, int C, int row_shape, int 
   if (!plan) return ILS_ERR_INVALID_ARG;
   const int rc = check_size(plan, H, W, C);
   if (rc != ILS_OK) return rc;
-  if (row_shape < 0 || row_shape >= find_ops(W / 2)->nrow || col_shape < 0 || col_shape >= find_ops(H)->ncol)
-    return ILS_ERR_INVALID_ARG;
+  int nr = 1, nc = 1;
+  (void)ils_shape_variants(H, W, &nr, &nc);
+  if (row_shape < 0 || row_shape >= nr || col_shape < 0 || col_shape >= nc) return ILS_ERR_INVALID_ARG;
+  if (frame_generic(H, W)) return ILS_OK;
   plan->tuned[size_key(H, W, C)] = {row_shape, col_shape};
   return ILS_OK;
 }
@@ -1036,9 +1235,19 @@ int ils_smooth_batch(ils_plan* plan, const ils_frame* frames, int n) {
     int N, pen, first, lane;
     bool big;
     WorkList row, fin, col;
+    // the part as one persistent launch (fo != nullptr): its frames' channel
+    // count (uniform C0, else prefix sums at chs in the header), control block
+    const ilsk::PersistOps* fo;
+    int C0;
+    long long channels;
+    const int* chs;
+    int* ctl;
+    FrameDesc d0;  // the part's first frame (its size)
   };
   std::vector<Launch> launches;
   std::vector<size_t> offs;  // (desc, row starts, fin starts, col starts) per class
+  std::vector<long long> chs_offs;  // channel prefix sums of a persistent part with mixed channel counts, or -1
+  size_t ctl_used = 0;  // ints of the persistent control area taken
   for (const Class& cl : classes) {
     Launch L;
     // shapes are tuned for the class's whole work (all channels of all its
@@ -1074,13 +1283,39 @@ int ils_smooth_batch(ils_plan* plan, const ils_frame* frames, int n) {
     offs.push_back(put(srow.data(), srow.size() * sizeof(int)));
     offs.push_back(put(sfin.data(), sfin.size() * sizeof(int)));
     offs.push_back(put(scol.data(), scol.size() * sizeof(int)));
+    // the part as one persistent launch, when compiled for its size and its
+    // control block fits what is left of the control area
+    L.fo = persist_for(plan, cd[0], cl.N, ctot);
+    L.C0 = cd[0].C;
+    L.channels = ctot;
+    L.chs = nullptr;
+    L.ctl = nullptr;
+    L.d0 = cd[0];
+    chs_offs.push_back(-1);
+    if (L.fo) {
+      // whole 128-byte lines, so every ticket counter has a line of its own
+      const size_t need_ints = align_up(ilsk::kPersistCtlHead + (2 * (size_t)cl.N + 1) * (size_t)ctot, 32);
+      if (ctl_used + need_ints > kPersistCtlInts) {
+        L.fo = nullptr;
+      } else {
+        L.ctl = reinterpret_cast<int*>(plan->ws + kBatchListBytes) + ctl_used;
+        ctl_used += need_ints;
+        bool uniform = true;
+        std::vector<int> chs(1, 0);
+        for (const FrameDesc& d : cd) {
+          uniform = uniform && d.C == L.C0;
+          chs.push_back(chs.back() + d.C);
+        }
+        if (!uniform) chs_offs.back() = (long long)put(chs.data(), chs.size() * sizeof(int));
+      }
+    }
     const int nf = (int)cl.idx.size();
     L.row = WorkList{FrameDesc{}, nullptr, nullptr, nf, srow.back()};
     L.fin = WorkList{FrameDesc{}, nullptr, nullptr, nf, sfin.back()};
     L.col = WorkList{FrameDesc{}, nullptr, nullptr, nf, scol.back()};
     launches.push_back(L);
   }
-  if (hdr.size() > kBatchHeaderBytes) return ILS_ERR_WORKSPACE;
+  if (hdr.size() > kBatchListBytes) return ILS_ERR_WORKSPACE;
   for (size_t c = 0; c < launches.size(); ++c) {
     const FrameDesc* dd = reinterpret_cast<const FrameDesc*>(plan->ws + offs[4 * c]);
     launches[c].row.descs = dd;
@@ -1089,6 +1324,7 @@ int ils_smooth_batch(ils_plan* plan, const ils_frame* frames, int n) {
     launches[c].row.starts = reinterpret_cast<const int*>(plan->ws + offs[4 * c + 1]);
     launches[c].fin.starts = reinterpret_cast<const int*>(plan->ws + offs[4 * c + 2]);
     launches[c].col.starts = reinterpret_cast<const int*>(plan->ws + offs[4 * c + 3]);
+    if (chs_offs[c] >= 0) launches[c].chs = reinterpret_cast<const int*>(plan->ws + chs_offs[c]);
   }
   hipError_t e = stage_upload(plan, plan->ws, hdr.data(), hdr.size());
   if (e != hipSuccess) return record(plan, e);
@@ -1099,10 +1335,21 @@ int ils_smooth_batch(ils_plan* plan, const ils_frame* frames, int n) {
   // k + 1).
   int maxN = 0;
   for (const Launch& L : launches) maxN = L.N > maxN ? L.N : maxN;
+  // A part with a persistent launch runs its whole sequence in that one launch, in
+  // the place of its first pass.
+  auto persist_part = [&](const Launch& L, hipStream_t st) {
+    return enqueue_persist(plan, L.fo, L.row.descs, L.chs, L.d0, L.row.n, L.C0, L.channels, L.N, L.pen, L.first,
+                         L.ctl, st);
+  };
   auto enqueue_chain = [&](int lane, hipStream_t st) -> hipError_t {
     hipError_t r = hipSuccess;
     for (const Launch& L : launches) {
       if (L.lane != lane || !L.big) continue;
+      if (L.fo) {
+        r = persist_part(L, st);
+        if (r != hipSuccess) return r;
+        continue;
+      }
       r = timed(plan, 0, [&] { return L.pk.rv->launch(L.first, L.pen, L.row, st); });
       if (r != hipSuccess) return r;
       for (int n = 0; n < L.N; ++n) {
@@ -1117,17 +1364,20 @@ int ils_smooth_batch(ils_plan* plan, const ils_frame* frames, int n) {
     }
     for (const Launch& L : launches) {
       if (L.lane != lane || L.big) continue;
-      r = timed(plan, 0, [&] { return L.pk.rv->launch(L.first, L.pen, L.row, st); });
+      if (L.fo)
+        r = persist_part(L, st);
+      else
+        r = timed(plan, 0, [&] { return L.pk.rv->launch(L.first, L.pen, L.row, st); });
       if (r != hipSuccess) return r;
     }
     for (int n = 0; n < maxN; ++n) {
       for (const Launch& L : launches) {
-        if (L.lane != lane || L.big || n >= L.N) continue;
+        if (L.lane != lane || L.big || L.fo || n >= L.N) continue;
         r = timed(plan, 3, [&] { return L.pk.cv->launch(L.col, st); });
         if (r != hipSuccess) return r;
       }
       for (const Launch& L : launches) {
-        if (L.lane != lane || L.big || n >= L.N) continue;
+        if (L.lane != lane || L.big || L.fo || n >= L.N) continue;
         if (n + 1 < L.N)
           r = timed(plan, 1, [&] { return L.pk.rv->launch(ilsk::ROW_MID, L.pen, L.row, st); });
         else
@@ -1164,6 +1414,9 @@ int ils_smooth_batch(ils_plan* plan, const ils_frame* frames, int n) {
     sig.push_back(L.row.total);
     sig.push_back(L.fin.total);
     sig.push_back(L.col.total);
+    sig.push_back((long long)(uintptr_t)L.fo);
+    sig.push_back((long long)(uintptr_t)L.ctl);
+    sig.push_back((long long)(uintptr_t)L.chs);
   }
   for (size_t o : offs) sig.push_back((long long)o);
   size_t hit = 0;
@@ -1201,6 +1454,31 @@ int ils_smooth_batch(ils_plan* plan, const ils_frame* frames, int n) {
   return record(plan, hipGraphLaunch(plan->graphs.front().exec, plan->stream));
 }
 
+int ils_enqueue_pass(ils_plan* plan, int kind, const float* f, float* out, int H, int W, int C, float lambda,
+                     float p, float eps) {
+  if (!plan || !f || !out || kind < 0 || kind > 3) return ILS_ERR_INVALID_ARG;
+  int rc = check_params(lambda, p, eps, 1);
+  if (rc == ILS_OK) rc = check_size(plan, H, W, C);
+  if (rc != ILS_OK) return rc;
+  if (plan->ws_bytes < kBatchHeaderBytes + frame_ws_bytes(H, W, C)) return ILS_ERR_WORKSPACE;
+  FrameDesc d;
+  fill_desc(plan, d, H, W, C, lambda, p, eps);
+  d.f = d.u0 = f;
+  d.out = out;
+  char* base = plan->ws + kBatchHeaderBytes;
+  d.specA = reinterpret_cast<cf*>(base);
+  d.specB = reinterpret_cast<cf*>(base + (size_t)C * H * d.ldS * sizeof(cf));
+  const Pick pk = choose(plan, d);
+  hipError_t e;
+  if (kind == 3) {
+    e = pk.cv->launch(one_frame(d, col_items(pk.cv, d)), plan->stream);
+  } else {
+    const int mode = kind == 0 ? ilsk::ROW_FIRST_SAME : kind == 1 ? ilsk::ROW_MID : ilsk::ROW_FINAL;
+    e = pk.rv->launch(mode, ilsk::PEN_CHARBONNIER, one_frame(d, row_items(pk.rv, mode, d)), plan->stream);
+  }
+  return record(plan, e);
+}
+
 // ------------------------------------------------------------ debug passes
 int ils_debug_rhs_spectrum(ils_plan* plan, const float* f, const float* u0, int H, int W, int C,
                            float lambda, float p, float eps, float* spec) {
@@ -1217,10 +1495,12 @@ int ils_debug_rhs_spectrum(ils_plan* plan, const float* f, const float* u0, int 
   char* base = plan->ws + kBatchHeaderBytes;
   d.specA = reinterpret_cast<cf*>(base);
   d.specB = reinterpret_cast<cf*>(base + (size_t)C * H * d.ldS * sizeof(cf));
-  const RowVariant* v = &find_ops(W / 2)->row[0];
+  // the runtime-length first pass writes the second half spectrum
+  const RowVariant* v = default_pick(H, W).rv;
+  const cf* res = frame_generic(H, W) ? d.specB : d.specA;
   hipError_t e = v->launch(ilsk::ROW_FIRST, ilsk::PEN_CHARBONNIER, one_frame(d, row_items(v, ilsk::ROW_FIRST, d)), plan->stream);
   if (e == hipSuccess)
-    e = hipMemcpy2DAsync(spec, (size_t)(W / 2 + 1) * sizeof(cf), d.specA, (size_t)d.ldS * sizeof(cf),
+    e = hipMemcpy2DAsync(spec, (size_t)(W / 2 + 1) * sizeof(cf), res, (size_t)d.ldS * sizeof(cf),
                          (size_t)(W / 2 + 1) * sizeof(cf), (size_t)C * H, hipMemcpyDeviceToDevice,
                          plan->stream);
   return record(plan, e);
@@ -1241,9 +1521,11 @@ int ils_debug_column_solve(ils_plan* plan, const float* spec_in, int H, int W, i
   d.specA = reinterpret_cast<cf*>(base);
   d.specB = reinterpret_cast<cf*>(base + (size_t)C * H * d.ldS * sizeof(cf));
   const size_t rowb = (size_t)(W / 2 + 1) * sizeof(cf);
-  hipError_t e = hipMemcpy2DAsync(d.specA, (size_t)d.ldS * sizeof(cf), spec_in, rowb, rowb,
+  // the runtime-length column pass works in place on the second half spectrum
+  cf* in = frame_generic(H, W) ? d.specB : d.specA;
+  hipError_t e = hipMemcpy2DAsync(in, (size_t)d.ldS * sizeof(cf), spec_in, rowb, rowb,
                                   (size_t)C * H, hipMemcpyDeviceToDevice, plan->stream);
-  const ColVariant* cv = &find_ops(H)->col[0];
+  const ColVariant* cv = default_pick(H, W).cv;
   if (e == hipSuccess) e = cv->launch(one_frame(d, col_items(cv, d)), plan->stream);
   if (e == hipSuccess)
     e = hipMemcpy2DAsync(spec_out, rowb, d.specB, (size_t)d.ldS * sizeof(cf), rowb, (size_t)C * H,
@@ -1266,7 +1548,7 @@ int ils_debug_row_inverse(ils_plan* plan, const float* spec, int H, int W, int C
   const size_t rowb = (size_t)(W / 2 + 1) * sizeof(cf);
   hipError_t e = hipMemcpy2DAsync(d.specB, (size_t)d.ldS * sizeof(cf), spec, rowb, rowb, (size_t)C * H,
                                   hipMemcpyDeviceToDevice, plan->stream);
-  const RowVariant* v = &find_ops(W / 2)->row[0];
+  const RowVariant* v = default_pick(H, W).rv;
   if (e == hipSuccess) e = v->launch(ilsk::ROW_FINAL, ilsk::PEN_CHARBONNIER, one_frame(d, row_items(v, ilsk::ROW_FINAL, d)), plan->stream);
   return record(plan, e);
 }

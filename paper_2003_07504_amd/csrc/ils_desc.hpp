@@ -3,7 +3,25 @@
 
 #include <cstdint>
 
+// Global (address space 1) qualifier for device pointers.  Pointers that
+// reach a kernel inside a descriptor are otherwise generic, and the compiler
+// then emits FLAT memory instructions, which also count against the LDS
+// wait counter: every wait for an LDS result would wait for outstanding
+// image and spectrum loads too.
+// (The host pass of the compiler parses the device code too; there the
+// qualifier means nothing and is left out.)
+#if defined(__HIP_DEVICE_COMPILE__)
+#define ILS_G __attribute__((address_space(1)))
+#else
+#define ILS_G
+#endif
+
 namespace ilsk {
+
+template <class T>
+__host__ __device__ __forceinline__ ILS_G T* gm(T* p) {
+  return (ILS_G T*)p;
+}
 
 struct cf;
 

@@ -195,7 +195,7 @@ __device__ __forceinline__ cf turn_half() {
 // applies the twiddle exp(2 pi i t k1 / M) and writes the exchange row
 // [k1][t].
 template <int P, int Q>
-__device__ __forceinline__ void c2r_stage_a(const cf* X, int k1, cf w1, cf (&v)[Q]) {
+__device__ __forceinline__ void c2r_stage_a(const ILS_G cf* X, int k1, cf w1, cf (&v)[Q]) {
   constexpr int M = P * Q;
   static_for<Q>([&](auto k2c) {
     constexpr int k2 = decltype(k2c)::value;
@@ -249,7 +249,7 @@ __device__ __forceinline__ void c2r_stage_b(const cf* slc, int t, cf (&z)[P]) {
 // X'[k] = E - i W_2M^k D with E = Z[k] + conj Z[M-k], D = Z[k] - conj Z[M-k]
 // (X' = 2 X), k = lane + T i <= M;  W_2M^k = W_2M^lane * W_2M^(T i).
 template <int P, int Q>
-__device__ __forceinline__ void r2c_post(const cf* slc, int lane, cf wl, cf* Xo) {
+__device__ __forceinline__ void r2c_post(const cf* slc, int lane, cf wl, ILS_G cf* Xo) {
   using Geo = RowGeom<P, Q>;
   constexpr int M = Geo::M, T = Geo::T;
   // every element but the last is in range (T (NPOST - 1) <= M), so only the
@@ -295,19 +295,19 @@ __device__ __forceinline__ void row_body(const FrameDesc& d, int band, int ch, f
   if (!in_slot) yrow = 0;
   const bool out_slot = slot >= 1 && slot <= Gv;
   const int yout = out_slot ? y0 - 1 + slot : 0;
-  const float2* frow = reinterpret_cast<const float2*>(d.f + (size_t)ch * H * W + (size_t)yout * W);
+  const ILS_G float2* frow = reinterpret_cast<const ILS_G float2*>(gm(d.f) + (size_t)ch * H * W + (size_t)yout * W);
 
   // per-lane factors of the real-FFT twiddles (one load each, issued first)
-  const cf w2lane = d.tw2_row[lane];  // exp(-i pi lane / M)
+  const cf w2lane = gm(d.tw2_row)[lane];  // exp(-i pi lane / M)
   // twiddle table -> LDS
-  for (int i = tid; i < P * Geo::QP; i += blockDim.x) tws[i] = d.twm_row[i];
+  for (int i = tid; i < P * Geo::QP; i += blockDim.x) tws[i] = gm(d.twm_row)[i];
 
   float2 fv[P];
   // u^0 = f (Algorithm 1): the data term is the slot's own u row in LDS
   constexpr bool f_is_u0 = (MODE == ROW_FIRST_SAME);
   if constexpr (MODE == ROW_FIRST || MODE == ROW_FIRST_SAME) {
     if (in_slot && lane < Q) {  // u^0 row of this slot, all loads in flight together
-      const float2* urow = reinterpret_cast<const float2*>(d.u0 + (size_t)ch * H * W + (size_t)yrow * W);
+      const ILS_G float2* urow = reinterpret_cast<const ILS_G float2*>(gm(d.u0) + (size_t)ch * H * W + (size_t)yrow * W);
       float2 uv[P];
       static_for<P>([&](auto n1c) {
         constexpr int n1 = decltype(n1c)::value;
@@ -330,7 +330,7 @@ __device__ __forceinline__ void row_body(const FrameDesc& d, int band, int ch, f
     // ---- C2R of this slot's row (its loads overlap the table load)
     cf v[Q];
     if (in_slot && lane < P) {
-      const cf* X = d.specB + (size_t)ch * H * ldS + (size_t)yrow * ldS;
+      const ILS_G cf* X = gm(d.specB) + (size_t)ch * H * ldS + (size_t)yrow * ldS;
       c2r_stage_a<P, Q>(X, lane, cf{w2lane.x, -w2lane.y}, v);
     }
     __syncthreads();  // twiddle table ready
@@ -455,7 +455,7 @@ __device__ __forceinline__ void row_body(const FrameDesc& d, int band, int ch, f
     });
   }
   slot_sync<T>();
-  if (out_slot) r2c_post<P, Q>(slc, lane, w2lane, d.specA + (size_t)ch * H * ldS + (size_t)yout * ldS);
+  if (out_slot) r2c_post<P, Q>(slc, lane, w2lane, gm(d.specA) + (size_t)ch * H * ldS + (size_t)yout * ldS);
 }
 
 // --------------------------------------------------------------------------
@@ -478,11 +478,11 @@ __device__ __forceinline__ void row_final_body(const FrameDesc& d, int band, int
   cf* tws = reinterpret_cast<cf*>(smem + G * SLOT_F);
   const bool in_slot = slot < Gv;
   const int yrow = in_slot ? y0 + slot : 0;
-  const cf w2lane = d.tw2_row[lane];
-  for (int i = tid; i < P * Geo::QP; i += blockDim.x) tws[i] = d.twm_row[i];
+  const cf w2lane = gm(d.tw2_row)[lane];
+  for (int i = tid; i < P * Geo::QP; i += blockDim.x) tws[i] = gm(d.twm_row)[i];
   cf v[Q];
   if (in_slot && lane < P) {
-    const cf* X = d.specB + (size_t)ch * H * ldS + (size_t)yrow * ldS;
+    const ILS_G cf* X = gm(d.specB) + (size_t)ch * H * ldS + (size_t)yrow * ldS;
     c2r_stage_a<P, Q>(X, lane, cf{w2lane.x, -w2lane.y}, v);
   }
   __syncthreads();  // twiddle table ready
@@ -491,10 +491,10 @@ __device__ __forceinline__ void row_final_body(const FrameDesc& d, int band, int
   if (in_slot && lane < Q) {
     cf z[P];
     c2r_stage_b<P, Q>(slc, lane, z);
-    float2* orow = reinterpret_cast<float2*>(d.out + (size_t)ch * H * W + (size_t)yrow * W);
+    ILS_G float2* orow = reinterpret_cast<ILS_G float2*>(gm(d.out) + (size_t)ch * H * W + (size_t)yrow * W);
     const float k = d.boost;
     if (k != 0.0f) {  // detail enhancement: u + k (f - u); each element is read before it is written
-      const float2* frow = reinterpret_cast<const float2*>(d.f + (size_t)ch * H * W + (size_t)yrow * W);
+      const ILS_G float2* frow = reinterpret_cast<const ILS_G float2*>(gm(d.f) + (size_t)ch * H * W + (size_t)yrow * W);
       static_for<P>([&](auto n1c) {
         constexpr int n1 = decltype(n1c)::value;
         const float2 fv = frow[Q * n1 + lane];
@@ -528,8 +528,8 @@ __device__ __forceinline__ void col_body(const FrameDesc& d, int tile, int ch, f
   const int c = tile * S + s;
   const bool col_ok = c < Wh;
   const int cc = col_ok ? c : 0;
-  const cf* in = d.specA + (size_t)ch * H * ldS + cc;
-  cf* out = d.specB + (size_t)ch * H * ldS + cc;
+  const ILS_G cf* in = gm(d.specA) + (size_t)ch * H * ldS + cc;
+  ILS_G cf* out = gm(d.specB) + (size_t)ch * H * ldS + cc;
   cf* ex = reinterpret_cast<cf*>(smem);
   cf* tws = reinterpret_cast<cf*>(smem + Geo::EX_F);  // matrix [k1][j] (row stride QT) or vector [l]
   float* syl = smem + Geo::EX_F + 2 * P * QT;          // Sy[l] (matrix layout only)
@@ -538,15 +538,15 @@ __device__ __forceinline__ void col_body(const FrameDesc& d, int tile, int ch, f
   if (j < Q) {  // stage A loads first: lane n2 = j, rows Q n1 + n2
     static_for<P>([&](auto n1c) {
       constexpr int n1 = decltype(n1c)::value;
-      x[n1] = col_ok ? in[(size_t)(Q * n1 + j) * ldS] : cf{0.0f, 0.0f};
+      x[n1] = col_ok ? cf(in[(size_t)(Q * n1 + j) * ldS]) : cf{0.0f, 0.0f};
     });
   }
-  const float sxk = d.sx[cc];
+  const float sxk = gm(d.sx)[cc];
   if constexpr (Geo::MAT) {
-    for (int i = tid; i < P * QT; i += blockDim.x) tws[i] = d.twm_col[i];
-    for (int i = tid; i < H; i += blockDim.x) syl[i] = d.sy[i];
+    for (int i = tid; i < P * QT; i += blockDim.x) tws[i] = gm(d.twm_col)[i];
+    for (int i = tid; i < H; i += blockDim.x) syl[i] = gm(d.sy)[i];
   } else {
-    for (int i = tid; i < H; i += blockDim.x) tws[i] = d.tw_col[i];
+    for (int i = tid; i < H; i += blockDim.x) tws[i] = gm(d.tw_col)[i];
   }
   __syncthreads();
   if (j < Q) {

@@ -85,6 +85,11 @@ class Plan:
         check(self._lib.ils_plan_set_stream(self._h, ctypes.c_void_p(_stream_ptr(self.device))),
               "ils_plan_set_stream")
 
+    def set_persistent(self, on: bool) -> None:
+        """Use (True, the default) or not the single-launch pass sequence of
+        the sizes compiled with one."""
+        check(self._lib.ils_plan_set_persistent(self._h, 1 if on else 0), "ils_plan_set_persistent")
+
     def last_error(self) -> int:
         return int(self._lib.ils_last_error(self._h))
 
@@ -99,6 +104,19 @@ class Plan:
         cnt = (ctypes.c_int * 4)()
         check(self._lib.ils_profile_end(self._h, tot, cnt), "ils_profile_end")
         return {k: (tot[i], cnt[i]) for i, k in enumerate(self.PASS_KINDS)}
+
+    def enqueue_pass(self, kind: str, f: torch.Tensor, lam: float, p: float, eps: float = 1e-4,
+                     out: torch.Tensor | None = None) -> None:
+        """Enqueue one launch of one pass kind (see PASS_KINDS) of the
+        sequence smooth() runs for f, on the workspace spectra (timing only:
+        the spectra are left meaningless; the final pass writes out)."""
+        fc = _as_chw(f, "f")
+        oc = _as_chw(out if out is not None else torch.empty_like(f), "out")
+        C, H, W = fc.shape
+        self._bind_stream()
+        check(self._lib.ils_enqueue_pass(self._h, self.PASS_KINDS.index(kind), ctypes.c_void_p(fc.data_ptr()),
+                                         ctypes.c_void_p(oc.data_ptr()), H, W, C, float(lam), float(p),
+                                         float(eps)), "ils_enqueue_pass")
 
     # -- tile shapes -------------------------------------------------------
     def tune(self, H: int, W: int, C: int) -> tuple[int, int]:

@@ -81,14 +81,26 @@ def test_status_strings(L):
 
 
 @pytest.mark.parametrize("H,W", [(256, 256), (1080, 1920), (2160, 3840), (480, 640), (720, 1280), (8, 8),
-                                 (16, 16), (90, 120)])
+                                 (16, 16), (90, 120), (768, 1024), (600, 800), (450, 600), (81, 54),
+                                 (4096, 8192), (1000, 1920)])
 def test_config_sizes_supported(L, H, W):
     assert L.ils_size_supported(H, W) == 1
 
 
-@pytest.mark.parametrize("H,W", [(1080, 1921), (7, 8), (1, 8), (8, 1), (1080, 14), (1000, 1920)])
+@pytest.mark.parametrize("H,W", [(1080, 1921), (7, 8), (1, 8), (8, 1), (1080, 14), (1000, 1918), (543, 1024),
+                                 (4374, 16), (16, 8194), (8192, 8), (8, 2)])
 def test_unsupported_sizes(L, H, W):
     assert L.ils_size_supported(H, W) == 0
+
+
+def test_every_235_smooth_length_up_to_4096_is_supported(L):
+    def smooth(n):
+        for q in (2, 3, 5):
+            while n % q == 0:
+                n //= q
+        return n == 1
+    for n in range(0, 4200):
+        assert L.ils_length_supported(n) == (1 if (2 <= n <= 4096 and smooth(n)) else 0), n
 
 
 def test_compiled_lengths_are_235_smooth(L):
@@ -132,6 +144,7 @@ def test_null_plan_and_pointers_rejected(L):
     assert L.ils_last_error(None) == -1
     assert L.ils_rms_diff(None, None, None, None, 1, None) == -1
     assert L.ils_debug_rhs_spectrum(None, None, None, 8, 8, 1, 1.0, 0.8, 1e-4, None) == -1
+    assert L.ils_enqueue_pass(None, 1, None, None, 8, 8, 1, 1.0, 0.8, 1e-4) == -1
 
 
 def test_plan_create_rejects_bad_arguments_before_hip(L):
@@ -161,7 +174,8 @@ def test_workspace_bytes(L):
     assert L.ils_batch_workspace_bytes(arr, 2) == (1 << 20) + 2 * 480 * 336 * 8 + 2 * 3 * 1080 * 976 * 8
 
 
-@pytest.mark.parametrize("H,W,nr,nc", [(1080, 1920, 6, 4), (2160, 3840, 3, 2), (256, 256, 1, 1), (480, 640, 1, 4)])
+@pytest.mark.parametrize("H,W,nr,nc", [(1080, 1920, 6, 4), (2160, 3840, 3, 2), (256, 256, 1, 1), (480, 640, 1, 4),
+                                       (768, 1024, 1, 1), (450, 600, 1, 1)])
 def test_shape_variants(L, H, W, nr, nc):
     from paper_2003_07504_amd import ils
     assert ils.shape_variants(H, W) == (nr, nc)

@@ -247,3 +247,29 @@ def test_tone_map_rejects_bad_contrast(torch, ils):
     torch.cuda.synchronize()
     assert abs(float(out.mean()) - 1.0) < 1e-5
     plan.close()
+
+
+def test_larger_eps_converges_faster_on_gpu(torch, ils):
+    """Sec. 3.3.4: a larger eps gives a smaller c0 and a faster decrease of
+    the energy; with eps = 1e-2 one iteration reaches a larger share of the
+    30-iteration decrease than with eps = 1e-4 and 1e-5 (device iterations
+    and device energy, one iteration at a time)."""
+    _say("eps convergence trend 256x256 grey")
+    f = torch.from_numpy(voronoi_image(256, 256, 1, 40, 0.05, seed=0)).cuda()
+    plan = ils.Plan(256, 256, 1)
+    shares = {}
+    for eps in (1e-2, 1e-4, 1e-5):
+        u = f.clone()
+        nxt = torch.empty_like(f)
+        es = [plan.energy(f, u, 1.0, 0.8, eps)]
+        for _ in range(30):
+            plan.iterate_from(f, u, 1.0, 0.8, eps, 1, out=nxt)
+            u, nxt = nxt, u
+            es.append(plan.energy(f, u, 1.0, 0.8, eps))
+        es = [float(e) for e in torch.stack(es).cpu()]
+        assert all(b <= a * (1 + 1e-9) for a, b in zip(es, es[1:])), eps
+        shares[eps] = (es[0] - es[1]) / (es[0] - es[-1])
+    assert plan.last_error() == 0
+    plan.close()
+    _say(f"share of the 30-iteration decrease at N=1: {shares}")
+    assert shares[1e-2] > shares[1e-4] > shares[1e-5]

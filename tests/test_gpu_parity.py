@@ -52,9 +52,15 @@ def _gpu_smooth(torch, ils, f, lam, p, eps, N):
     return out
 
 
+# Sizes whose row or column length has no compiled split (runtime-length
+# passes): H generic; both generic; odd W/2 = 27 with H = 81; the maximum
+# column length 4096; the maximum row length W/2 = 4096.
+GENERIC_STAGE_SHAPES = [(768, 1024, 1), (450, 600, 2), (81, 54, 1), (4096, 8, 1), (6, 8192, 1)]
+
+
 # ------------------------------------------------------------ single passes
 @pytest.mark.parametrize("H,W,C", [(8, 8, 1), (16, 16, 2), (90, 120, 1), (256, 256, 1), (1080, 1920, 1),
-                                   (2160, 3840, 1), (480, 640, 1), (720, 1280, 1)])
+                                   (2160, 3840, 1), (480, 640, 1), (720, 1280, 1)] + GENERIC_STAGE_SHAPES)
 def test_stage_rhs_spectrum(torch, ils, H, W, C):
     _say(f"stage rhs H={H} W={W} C={C}")
     lam, p, eps = 1.3, 0.7, 1e-4
@@ -78,7 +84,7 @@ def test_stage_rhs_spectrum(torch, ils, H, W, C):
 
 
 @pytest.mark.parametrize("H,W,C", [(8, 8, 1), (16, 16, 1), (90, 120, 2), (256, 256, 1), (1080, 1920, 1),
-                                   (2160, 3840, 1), (480, 640, 1), (720, 1280, 1)])
+                                   (2160, 3840, 1), (480, 640, 1), (720, 1280, 1)] + GENERIC_STAGE_SHAPES)
 def test_stage_column_solve(torch, ils, H, W, C):
     _say(f"stage column H={H} W={W} C={C}")
     lam, p, eps = 0.9, 0.8, 1e-4
@@ -99,7 +105,7 @@ def test_stage_column_solve(torch, ils, H, W, C):
 
 
 @pytest.mark.parametrize("H,W,C", [(8, 8, 1), (16, 16, 1), (90, 120, 2), (256, 256, 1), (1080, 1920, 1),
-                                   (2160, 3840, 1), (480, 640, 1), (720, 1280, 1)])
+                                   (2160, 3840, 1), (480, 640, 1), (720, 1280, 1)] + GENERIC_STAGE_SHAPES)
 def test_stage_row_inverse(torch, ils, H, W, C):
     _say(f"stage row inverse H={H} W={W} C={C}")
     rng = np.random.default_rng(H * 3 + W)
@@ -133,6 +139,13 @@ CASES = [
     (1080, 1920, 3, 400, 0.05, 0.5, 0.2, 10, 22),
     (256, 256, 1, 40, 0.05, 1.0, 1.5, 4, 23),
     (1080, 1920, 3, 400, 0.05, 1.0, 1.5, 4, 24),
+    # runtime-length passes: 1024 x 768 RGB (H = 768), 800 x 600 (H = 600,
+    # W/2 = 400), odd W/2, and the maximum lengths
+    (768, 1024, 3, 100, 0.05, 1.0, 0.8, 4, 25),
+    (600, 800, 1, 60, 0.05, 2.0, 0.5, 4, 26),
+    (81, 54, 2, 8, 0.05, 1.0, 0.8, 4, 27),
+    (4096, 8, 1, 20, 0.05, 1.0, 0.8, 4, 28),
+    (6, 8192, 1, 20, 0.05, 1.0, 0.8, 4, 29),
 ]
 
 
@@ -258,7 +271,7 @@ def test_plan_limits_and_workspace(torch, ils):
     g = torch.zeros((2, 256, 256), device="cuda")
     with pytest.raises(IlsError):
         plan.smooth(g, 1.0, 0.8)
-    h = torch.zeros((1, 250, 256), device="cuda")
+    h = torch.zeros((1, 254, 256), device="cuda")  # 254 = 2 x 127: not 2/3/5-smooth
     with pytest.raises(IlsError):
         plan.smooth(h, 1.0, 0.8)
     plan.close()

@@ -50,6 +50,8 @@ CASES = [
     (540, 1024, 3, 20.0, 10 / 255, 10, "clipart"),
     (480, 640, 3, 30.0, 10 / 255, 15, "texture"),
     (1080, 1920, 1, 1.0, 0.05, 4, "voronoi"),
+    # the paper's texture image size, 600 x 450 (runtime-length passes: W/2 = 300, H = 450)
+    (450, 600, 3, 30.0, 10 / 255, 15, "texture"),
 ]
 
 
