@@ -302,6 +302,27 @@ int ils_shape_variants(int H, int W, int* n_row, int* n_col);
 int ils_plan_tune(ils_plan* plan, int H, int W, int C, int* row_shape, int* col_shape);
 int ils_plan_set_shapes(ils_plan* plan, int H, int W, int C, int row_shape, int col_shape);
 
+/* ---- allocation-free smoothing ----
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * computation of ils_smooth (Algorithm 1, no plan, default tile shapes)
+ * with its two half spectra in a file-scope device array of the library
+ * (64 MiB per GPU, held from the library's loading until the process ends)
+ * instead of a caller workspace (its first 4 MiB hold the transform tables
+ * of every supported length).  The first call on a device copies the tables
+ * into that array synchronously; later calls only enqueue on hip_stream.
+ * No call allocates or frees memory.
+ *   f, out : device pointers, C x H x W float32 (out == f allowed).
+ *   Frames whose two half spectra exceed ils_noalloc_max_bytes()
+ *   (2 * C * H * (W/2+1 rounded up to 16) * 8 bytes; a 1920 x 1080 RGB
+ *   frame fits, a 3840 x 2160 RGB frame does not) return ILS_ERR_WORKSPACE
+ *   before anything is enqueued.  Other rules and results as ils_smooth.
+ * Every call on one GPU uses the same array: calls that overlap on one GPU
+ * (other streams, other host threads) race and give undefined results. */
+size_t ils_noalloc_max_bytes(void);
+int ils_smooth_noalloc(const float* f, int H, int W, int C, float lambda, float p, float eps, int N, float* out,
+                       void* hip_stream);
+
 /* Destroy a plan (NULL is accepted).  Does not free the workspace. */
 int ils_plan_destroy(ils_plan* plan);
 

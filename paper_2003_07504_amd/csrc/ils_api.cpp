@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <functional>
 #include <map>
+#include <mutex>
 #include <string>
 #include <new>
 #include <vector>
@@ -1452,6 +1453,88 @@ int ils_smooth_batch(ils_plan* plan, const ils_frame* frames, int n) {
     plan->graphs.insert(plan->graphs.begin(), ils_plan::BatchGraph{sig, exec});
   }
   return record(plan, hipGraphLaunch(plan->graphs.front().exec, plan->stream));
+}
+
+}  // extern "C"
+
+// ------------------------------------------------- allocation-free variant
+// Device memory of ils_smooth_noalloc: the tables of every compiled length
+// (first kNoAllocTableBytes), then the two half spectra of one frame.  Each
+// GPU the library runs on holds its own copy until the process ends.
+constexpr size_t kNoAllocTableBytes = 4u << 20;
+constexpr size_t kNoAllocBytes = 64u << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+constexpr int kNoAllocDevices = 64;
+struct NoAllocDevice {
+  bool ready;
+  char* base;  // device address of `scratch` on this device
+  std::map<int, LenTables> tab;
+};
+NoAllocDevice g_noalloc[kNoAllocDevices];
+std::mutex g_noalloc_mu;
+
+// Set-up on the current device, once: the device address of `scratch`
+// (host code must not use the array's name as an address) and the tables,
+// copied into it synchronously.  Only this first call copies from the host.
+int noalloc_device(NoAllocDevice** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return ILS_ERR_HIP;
+  if (dev < 0 || dev >= kNoAllocDevices) return ILS_ERR_HIP;
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  NoAllocDevice& nd = g_noalloc[dev];
+  if (!nd.ready) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return ILS_ERR_HIP;
+    std::vector<char> host;
+    std::map<int, LenTables> tab;
+    build_tables(host, tab);
+    if (host.size() > kNoAllocTableBytes) return ILS_ERR_HIP;
+    if (hipMemcpy(ptr, host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess) return ILS_ERR_HIP;
+    nd.base = static_cast<char*>(ptr);
+    nd.tab = std::move(tab);
+    nd.ready = true;
+  }
+  *out = &nd;
+  return ILS_OK;
+}
+}  // namespace
+
+extern "C" {
+
+size_t ils_noalloc_max_bytes(void) { return kNoAllocBytes - kNoAllocTableBytes; }
+
+int ils_smooth_noalloc(const float* f, int H, int W, int C, float lambda, float p, float eps, int N, float* out,
+                       void* hip_stream) {
+  if (!f || !out) return ILS_ERR_INVALID_ARG;
+  int rc = check_params(lambda, p, eps, N);
+  if (rc != ILS_OK) return rc;
+  rc = check_size(nullptr, H, W, C);
+  if (rc != ILS_OK) return rc;
+  if (frame_ws_bytes(H, W, C) > kNoAllocBytes - kNoAllocTableBytes) return ILS_ERR_WORKSPACE;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  if (N == 0 || lambda == 0.0f) {
+    if (f == out) return ILS_OK;
+    return hipMemcpyAsync(out, f, (size_t)C * H * W * sizeof(float), hipMemcpyDeviceToDevice, st) == hipSuccess
+               ? ILS_OK
+               : ILS_ERR_HIP;
+  }
+  NoAllocDevice* nd = nullptr;
+  rc = noalloc_device(&nd);
+  if (rc != ILS_OK) return rc;
+  FrameDesc d;
+  fill_desc_on(nd->base, nd->tab, d, H, W, C, lambda, p, eps);
+  d.f = f;
+  d.u0 = f;
+  d.out = out;
+  char* spec = nd->base + kNoAllocTableBytes;
+  d.specA = reinterpret_cast<cf*>(spec);
+  d.specB = reinterpret_cast<cf*>(spec + (size_t)C * H * d.ldS * sizeof(cf));
+  // default tile shapes: no tuning (timing would create events)
+  const Pick pk = default_pick(H, W);
+  const hipError_t e = enqueue_frame(pk, d, N, ilsk::PEN_CHARBONNIER, st, [](int, auto&& launch) { return launch(); });
+  return e == hipSuccess ? ILS_OK : ILS_ERR_HIP;
 }
 
 int ils_enqueue_pass(ils_plan* plan, int kind, const float* f, float* out, int H, int W, int C, float lambda,
