@@ -56,6 +56,11 @@ def layer_shapes():
     return [((co, ci, 3, 3), (co,)) for ci, co in LAYERS]
 
 
+def layer_param_sizes():
+    """Parameters per layer (weights and bias) in the flat order."""
+    return [int(np.prod(ws)) + int(np.prod(bs)) for ws, bs in layer_shapes()]
+
+
 def param_count() -> int:
     return int(_lib().ils_net_param_count())
 

@@ -75,10 +75,19 @@ def test_forward_matches_oracle(torch, S, B, H, W):
         ref, _ = _emulated_forward(params, f[b].astype(np.float64), float(lam[b]), float(p[b]))
         z_ref = ref - f[b]
         z_got = got[b] - f[b]
-        err = np.max(np.abs(z_got - z_ref))
+        dz = np.abs(z_got - z_ref)
+        err = float(np.max(dz))
+        med = float(np.median(dz))
         scale = np.max(np.abs(z_ref)) + 1e-12
-        _say(f"  image {b}: max|dz| = {err:.3e}, max|z| = {scale:.3e}")
+        _say(f"  image {b}: max|dz| = {err:.3e}, median|dz| = {med:.3e}, max|z| = {scale:.3e}")
+        # Both sides round every activation to bf16; where fp32 summation
+        # order moves a value across a bf16 rounding boundary, that one value
+        # differs by a bf16 step (2^-8 relative) and the difference spreads
+        # through the later layers: measured up to 1.1e-2 max|z| on 270 x 482
+        # images, 1e-6 elsewhere.  Such flips are rare, so the median stays at
+        # the fp32 level (a wrong tap or index would move it to O(max|z|)).
         assert err <= 2e-2 * scale + 1e-6
+        assert med <= 1e-4 * scale
     net.close()
 
 
@@ -115,7 +124,8 @@ def test_gradients_match_oracle(torch, S, B, H, W):
         rel = np.linalg.norm(a - r) / (np.linalg.norm(r) + 1e-30)
         cos = float(a @ r / (np.linalg.norm(a) * np.linalg.norm(r) + 1e-30))
         _say(f"  layer {i}: rel_l2 = {rel:.3e} cos = {cos:.6f}")
-        assert rel < 5e-2 and cos > 0.998
+        # measured: rel_l2 <= 1.6e-4 with cos = 1.000000 (bf16 operands on both sides)
+        assert rel < 2e-3 and cos > 0.99999
         off += n
     net.close()
 
