@@ -63,6 +63,16 @@ __device__ __forceinline__ float mu_pen(float g, float a, float b, float l2r) {
 __device__ __forceinline__ float from_prev_lane(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138 /* wave_shr:1 */, 0xf, 0xf, false));
 }
+__device__ __forceinline__ float from_next_lane(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130 /* wave_shl:1 */, 0xf, 0xf, false));
+}
+// the value of the first lane of a T-lane slot (ds_swizzle bit mode)
+template <int T>
+__device__ __forceinline__ float from_slot_first_lane(float v) {
+  static_assert(T <= 32 && (T & (T - 1)) == 0, "slot must be a power of two within 32 lanes");
+  constexpr int pattern = 31 & ~(T - 1);  // and-mask, or-mask 0, xor-mask 0
+  return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), pattern));
+}
 template <int T>
 __device__ __forceinline__ float from_slot_last_lane(float v) {
   static_assert(T <= 32 && (T & (T - 1)) == 0, "slot must be a power of two within 32 lanes");
@@ -94,6 +104,19 @@ struct RowGeom {
   static constexpr int TAB_F = 2 * P * QP;   // twiddles exp(-2 pi i t k1 / M) at [k1][t]
   static constexpr int NPOST = (M + 1 + T - 1) / T;  // post-process elements per lane
 };
+
+// Waves per SIMD that the row-pass workgroups resident on a CU (as many as
+// fit its 160 KB of LDS, at most 8 per SIMD) need; each may then use
+// 512 / waves VGPRs.
+constexpr int resident_waves_per_simd(int threads, int lds_bytes) {
+  const int blocks = 163840 / lds_bytes;
+  const int waves = blocks * ((threads + 63) / 64);
+  return (waves + 3) / 4 > 8 ? 8 : (waves + 3) / 4;
+}
+template <int P, int Q, int G>
+constexpr int row_waves() {
+  return resident_waves_per_simd((G + 2) * RowGeom<P, Q>::T, 4 * ((G + 2) * RowGeom<P, Q>::SLOT_F + RowGeom<P, Q>::TAB_F));
+}
 
 // Rows per row-pass workgroup: two workgroups per CU (160 KB of LDS) when
 // that leaves bands of at least four rows, else one.
@@ -303,8 +326,16 @@ __device__ __forceinline__ void row_body(const FrameDesc& d, int band, int ch, f
   for (int i = tid; i < P * Geo::QP; i += blockDim.x) tws[i] = gm(d.twm_row)[i];
 
   float2 fv[P];
-  // u^0 = f (Algorithm 1): the data term is the slot's own u row in LDS
+  // u^0 = f (Algorithm 1): the data term is the slot's own u row
   constexpr bool f_is_u0 = (MODE == ROW_FIRST_SAME);
+  // When a slot is Q lanes of one wavefront (Q a power of two), mu_x is
+  // passed between lanes (below).  If moreover the shape leaves 256 VGPRs
+  // per lane (two waves per SIMD), each lane keeps its own pairs of u in
+  // registers for the stencil and takes the right neighbour from the next
+  // lane; only the row below comes from LDS.  Both read the same values.
+  constexpr bool kLaneReuse = (T == Q) && (T <= 32) && ((T & (T - 1)) == 0);
+  constexpr bool kRegRow = kLaneReuse && row_waves<P, Q, G>() <= 2;
+  float2 ur[P];
   if constexpr (MODE == ROW_FIRST || MODE == ROW_FIRST_SAME) {
     if (in_slot && lane < Q) {  // u^0 row of this slot, all loads in flight together
       const ILS_G float2* urow = reinterpret_cast<const ILS_G float2*>(gm(d.u0) + (size_t)ch * H * W + (size_t)yrow * W);
@@ -323,6 +354,7 @@ __device__ __forceinline__ void row_body(const FrameDesc& d, int band, int ch, f
       static_for<P>([&](auto n1c) {
         constexpr int n1 = decltype(n1c)::value;
         u2[Q * n1 + lane] = uv[n1];
+        if constexpr (kRegRow) ur[n1] = uv[n1];
       });
     }
     __syncthreads();
@@ -350,6 +382,7 @@ __device__ __forceinline__ void row_body(const FrameDesc& d, int band, int ch, f
       static_for<P>([&](auto n1c) {
         constexpr int n1 = decltype(n1c)::value;
         u2[Q * n1 + lane] = make_float2(z[n1].x, z[n1].y);
+        if constexpr (kRegRow) ur[n1] = make_float2(z[n1].x, z[n1].y);
       });
     }
     __syncthreads();
@@ -370,13 +403,27 @@ __device__ __forceinline__ void row_body(const FrameDesc& d, int band, int ch, f
       // mu_x left of pair j equals mu_x right of pair j - 1.  When a slot is
       // Q lanes of one wavefront, pair j - 1 sits in the previous lane (same
       // n1) or, for lane 0, in lane Q - 1 at n1 - 1: take it from there.
-      constexpr bool kLaneReuse = (T == Q) && (T <= 32) && ((T & (T - 1)) == 0);
+      // Likewise pair j + 1 (the right neighbour's first pixel) sits in the
+      // next lane, or for lane Q - 1 in lane 0 at n1 + 1 (at n1 = P - 1 that
+      // is pair 0, the periodic wrap).
       float mx1_prev = 0.0f;
       static_for<P>([&](auto n1c) {
         constexpr int n1 = decltype(n1c)::value;
         const int j = Q * n1 + t;
         const int jp = (j == M - 1) ? 0 : j + 1;
-        const float2 c = uc[j], dn = ud[j], rr = uc[jp];
+        float2 c, rr;
+        if constexpr (kRegRow) {
+          c = ur[n1];
+          constexpr int n1n = (n1 + 1) % P;
+          const float nx = from_next_lane(c.x);
+          const float wx = from_slot_first_lane<T>(ur[n1n].x);
+          rr.x = (t == Q - 1) ? wx : nx;
+          rr.y = 0.0f;
+        } else {
+          c = uc[j];
+          rr = uc[jp];
+        }
+        const float2 dn = ud[j];
         if (f_is_u0) fv[n1] = c;
         myd[n1] = make_float2(mu_pen<PEN>(dn.x - c.x, a_exp, inv_eps, l2r), mu_pen<PEN>(dn.y - c.y, a_exp, inv_eps, l2r));
         const float mx0 = mu_pen<PEN>(c.y - c.x, a_exp, inv_eps, l2r);
@@ -400,7 +447,12 @@ __device__ __forceinline__ void row_body(const FrameDesc& d, int band, int ch, f
       static_for<P>([&](auto n1c) {
         constexpr int n1 = decltype(n1c)::value;
         const int j = Q * n1 + t;
-        const float2 c = uc[j], dn = ud[j];
+        float2 c;
+        if constexpr (kRegRow)
+          c = ur[n1];
+        else
+          c = uc[j];
+        const float2 dn = ud[j];
         myd[n1] = make_float2(mu_pen<PEN>(dn.x - c.x, a_exp, inv_eps, l2r), mu_pen<PEN>(dn.y - c.y, a_exp, inv_eps, l2r));
       });
     }
