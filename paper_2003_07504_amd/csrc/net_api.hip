@@ -115,30 +115,45 @@ __global__ void k_loss_final(const double* partial, int nb, double n, float* los
   }
 }
 
-// Partial weight and bias gradients of one convolution (fp32 VALU):
-//   dW[co][ci][tap] = sum_pixels g[pixel][co] x[pixel + shift(tap)][ci],  db[co] = sum g[pixel][co]
-// Thread (co pair, ci pair) keeps 2 x 2 x 9 accumulators; blocks stride over
-// TH x TW pixel tiles and write one partial row each (reduced in a fixed order
-// afterwards, so the result is deterministic).
+// Partial weight and bias gradients of one convolution on the MFMA units:
+//   dW[co][ci][tap] = sum_pixels g[pixel][co] x[pixel + shift(tap)][ci]
+// is, for each tap, D[co][ci] += sum_k G[co][k] X_tap[k][ci] with k running
+// over the 32 pixels of one tile row (one K block of v_mfma_f32_16x16x32_bf16).
+// The (16-row co block, 16-column ci block) pairs are dealt to the four
+// waves; when there are two pairs (first and last layers), two waves share a
+// pair, taking alternate tile rows, and add up through LDS at the end.  The
+// fragments are gathered from the NHWC tiles in LDS (channels beyond the
+// layer's read as zero).  db[co] = sum g[pixel][co] on the VALU.  Blocks
+// stride over TH x TW pixel tiles and write one partial row each (reduced
+// in a fixed order afterwards: deterministic).
 template <int GC, int XC>
-__global__ void __launch_bounds__(256) k_wgrad(const bf16* g, const bf16* x, float* partial, int gcr, int xcr,
-                                              int B, int H, int W) {
+__global__ void __launch_bounds__(256) k_wgrad_mfma(const bf16* g, const bf16* x, float* partial, int gcr, int xcr,
+                                                   int B, int H, int W) {
   constexpr int LH = TH + 2, LW = TW + 2;
-  __shared__ __attribute__((aligned(16))) bf16 gt[TH * TW * GC];
-  __shared__ __attribute__((aligned(16))) bf16 xt[LH * LW * XC];
-  constexpr int NI2 = XC / 2;
+  constexpr int MB = (GC + 15) / 16, NB = (XC + 15) / 16;
+  constexpr int PAIRS = MB * NB;  // 2 or 4
+  constexpr int RG = 4 / PAIRS;   // waves per pair
+  static_assert(PAIRS * RG == 4, "four waves per block");
+  constexpr int G_BYTES = TH * TW * GC * 2, X_BYTES = LH * LW * XC * 2;
+  constexpr int RED_BYTES = 2 * 64 * 36 * 4;  // accumulators of two waves
+  constexpr int LDS_BYTES = (G_BYTES + X_BYTES) > RED_BYTES ? (G_BYTES + X_BYTES) : RED_BYTES;
+  __shared__ __attribute__((aligned(16))) unsigned char lds[LDS_BYTES];
+  __shared__ float bred[256];
+  bf16* gt = reinterpret_cast<bf16*>(lds);
+  bf16* xt = reinterpret_cast<bf16*>(lds + G_BYTES);
   const int tid = threadIdx.x;
-  const bool active = tid < (GC / 2) * NI2;
-  const int cp = tid / NI2, ip = tid - (tid / NI2) * NI2;
-  const int co0 = 2 * cp, ci0 = 2 * ip;
-  float acc[2][2][9];
-  float accb[2] = {0.f, 0.f};
+  const int wave = tid >> 6, lane = tid & 63;
+  const int pair = wave % PAIRS, rg = wave / PAIRS;
+  const int mb = pair / NB, nb = pair - mb * NB;
+  const int m = lane & 15, kc = lane >> 4;
+  const int co_a = mb * 16 + m;   // A row of this lane
+  const int ci_b = nb * 16 + m;   // B column of this lane
+  f32x4 acc[9];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int k = 0; k < 9; ++k) acc[i][j][k] = 0.f;
+  for (int tap = 0; tap < 9; ++tap) acc[tap] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float accb = 0.0f;
+  const int bco = tid % GC;  // bias: channel and pixel phase of this thread
+  const int bph = tid / GC;
 
   const int tiles_x = (W + TW - 1) / TW, tiles_y = (H + TH - 1) / TH;
   const int ntiles = B * tiles_x * tiles_y;
@@ -164,45 +179,52 @@ __global__ void __launch_bounds__(256) k_wgrad(const bf16* g, const bf16* x, flo
           *reinterpret_cast<const uint4*>(&x[((size_t)img * plane + (size_t)gy * W + gx) * XC + chn * 8]);
     }
     __syncthreads();
-    if (active) {
-      for (int py = 0; py < TH; ++py) {
-        for (int px = 0; px < TW; ++px) {
-          const int gi = (py * TW + px) * GC + co0;
-          const float g0 = bf2f(gt[gi]), g1 = bf2f(gt[gi + 1]);
-          accb[0] += g0;
-          accb[1] += g1;
+    for (int p = bph; p < TH * TW; p += 256 / GC) accb += bf2f(gt[p * GC + bco]);
+    for (int py = rg; py < TH; py += RG) {
+      bf16x8 a;
 #pragma unroll
-          for (int ta = 0; ta < 3; ++ta) {
+      for (int e = 0; e < 8; ++e) a[e] = co_a < GC ? gt[(py * TW + kc * 8 + e) * GC + co_a] : f2bf(0.0f);
 #pragma unroll
-            for (int tc = 0; tc < 3; ++tc) {
-              const int xi = ((py + ta) * LW + px + tc) * XC + ci0;
-              const float x0v = bf2f(xt[xi]), x1v = bf2f(xt[xi + 1]);
-              const int tap = ta * 3 + tc;
-              acc[0][0][tap] = fmaf(g0, x0v, acc[0][0][tap]);
-              acc[0][1][tap] = fmaf(g0, x1v, acc[0][1][tap]);
-              acc[1][0][tap] = fmaf(g1, x0v, acc[1][0][tap]);
-              acc[1][1][tap] = fmaf(g1, x1v, acc[1][1][tap]);
-            }
-          }
-        }
+      for (int tap = 0; tap < 9; ++tap) {
+        const int ta = tap / 3, tc = tap - 3 * ta;
+        bf16x8 b;
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+          b[e] = ci_b < XC ? xt[((py + ta) * LW + kc * 8 + e + tc) * XC + ci_b] : f2bf(0.0f);
+        acc[tap] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[tap], 0, 0, 0);
       }
     }
     __syncthreads();
   }
-  if (!active) return;
+  // waves of the second row group hand their sums to the first
+  float* red = reinterpret_cast<float*>(lds);
+  if (RG == 2 && rg == 1) {
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) red[((pair * 9 + tap) * 4 + i) * 64 + lane] = acc[tap][i];
+  }
+  bred[tid] = accb;
+  __syncthreads();
   float* out = partial + (size_t)blockIdx.x * (size_t)(gcr * xcr * 9 + gcr);
+  if (rg == 0) {
+    const int ci = nb * 16 + m;
 #pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    const int co = co0 + i;
-    if (co >= gcr) continue;
+    for (int i = 0; i < 4; ++i) {
+      const int co = mb * 16 + 4 * kc + i;
+      if (co >= gcr || ci >= xcr) continue;
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int ci = ci0 + j;
-      if (ci >= xcr) continue;
-#pragma unroll
-      for (int tap = 0; tap < 9; ++tap) out[((size_t)co * xcr + ci) * 9 + tap] = acc[i][j][tap];
+      for (int tap = 0; tap < 9; ++tap) {
+        float v = acc[tap][i];
+        if (RG == 2) v += red[((pair * 9 + tap) * 4 + i) * 64 + lane];
+        out[((size_t)co * xcr + ci) * 9 + tap] = v;
+      }
     }
-    if (ip == 0) out[(size_t)gcr * xcr * 9 + co] = accb[i];
+  }
+  if (tid < gcr) {
+    float sb = 0.0f;
+    for (int j = 0; j < 256 / GC; ++j) sb += bred[j * GC + tid];
+    out[(size_t)gcr * xcr * 9 + tid] = sb;
   }
 }
 
@@ -424,11 +446,14 @@ hipError_t run_backward(ils_net* n, const float* t, int B, int H, int W) {
     const bf16* x = n->act[i];
     const int len = L.co * L.ci * 9 + L.co;
     if (i == 5)
-      hipLaunchKernelGGL((k_wgrad<8, 32>), dim3(kWgradBlocks), dim3(256), 0, st, g, x, n->partial, L.co, L.ci, B, H, W);
+      hipLaunchKernelGGL((k_wgrad_mfma<8, 32>), dim3(kWgradBlocks), dim3(256), 0, st, g, x, n->partial, L.co, L.ci, B,
+                         H, W);
     else if (i == 0)
-      hipLaunchKernelGGL((k_wgrad<32, 8>), dim3(kWgradBlocks), dim3(256), 0, st, g, x, n->partial, L.co, L.ci, B, H, W);
+      hipLaunchKernelGGL((k_wgrad_mfma<32, 8>), dim3(kWgradBlocks), dim3(256), 0, st, g, x, n->partial, L.co, L.ci, B,
+                         H, W);
     else
-      hipLaunchKernelGGL((k_wgrad<32, 32>), dim3(kWgradBlocks), dim3(256), 0, st, g, x, n->partial, L.co, L.ci, B, H, W);
+      hipLaunchKernelGGL((k_wgrad_mfma<32, 32>), dim3(kWgradBlocks), dim3(256), 0, st, g, x, n->partial, L.co, L.ci,
+                         B, H, W);
     e = hipGetLastError();
     if (e != hipSuccess) break;
     hipLaunchKernelGGL(k_reduce_partials, dim3((len + 255) / 256), dim3(256), 0, st, n->partial, kWgradBlocks, len,
