@@ -295,6 +295,7 @@ static void fill_desc_on(const char* tables, const std::map<int, LenTables>& tab
   d.log2_r = 0.0f;
   d.col_scale = (float)(1.0 / (2.0 * (double)H * (double)W));
   d.boost = 0.0f;
+  d.nb_row = 0;
 }
 static void fill_desc(const ils_plan* plan, FrameDesc& d, int H, int W, int C, float lambda, float p, float eps) {
   fill_desc_on(plan->tables, plan->tab, d, H, W, C, lambda, p, eps);
@@ -405,8 +406,7 @@ static WorkList one_frame(const FrameDesc& d, int items) {
   return wl;
 }
 static int row_items(const RowVariant* v, int mode, const FrameDesc& d) {
-  const int g = v->rows[mode];
-  return d.C * ((d.H + g - 1) / g);
+  return d.C * ilsk::row_bands(d, v->rows[mode]);
 }
 static int col_items(const ColVariant* v, const FrameDesc& d) {
   const int s = v->cols;
@@ -489,6 +489,23 @@ static float time_launches(ils_plan* plan, const std::function<hipError_t()>& la
 // every pass on the runtime-length kernels.
 static bool frame_generic(int H, int W) { return !find_ops(W / 2) || !find_ops(H); }
 
+// Row bands of a single frame on `cus` compute units with row shape v: the
+// fewest rounds of one block per CU that the shape's full bands need, filled
+// with as many (shorter, balanced) bands as they hold, but bands of at least
+// four rows (or the shape's height, if less).  The blocks of a round then
+// end together instead of the last round running a few blocks alone.  The
+// runtime-length kernels keep their own bands.
+static FrameDesc banded(int cus, const RowVariant* v, FrameDesc d) {
+  d.nb_row = 0;
+  if (cus <= 0 || frame_generic(d.H, d.W)) return d;
+  const int g = v->rows[ilsk::ROW_MID];
+  const int lo = (d.H + g - 1) / g;
+  const long long rounds = ((long long)d.C * lo + cus - 1) / cus;
+  const int hi = std::max(lo, d.H / std::min(g, 4));
+  d.nb_row = (int)std::max<long long>(lo, std::min<long long>(rounds * cus / d.C, hi));
+  return d;
+}
+
 // Default shapes (no tuning).
 static Pick default_pick(int H, int W) {
   if (frame_generic(H, W)) {
@@ -523,7 +540,8 @@ static Pick choose(ils_plan* plan, const FrameDesc& d) {
       t.out = reinterpret_cast<float*>(t.specB);
       float bestr = 1e30f, bestc = 1e30f;
       for (int v = 0; v < orow->nrow; ++v) {
-        const WorkList wl = one_frame(t, row_items(&orow->row[v], ilsk::ROW_MID, t));
+        const FrameDesc tb = banded(plan->cus, &orow->row[v], t);
+        const WorkList wl = one_frame(tb, row_items(&orow->row[v], ilsk::ROW_MID, tb));
         const float ms = time_launches(plan, [&] { return orow->row[v].launch(ilsk::ROW_MID, ilsk::PEN_CHARBONNIER, wl, plan->stream); });
         if (ms >= 0.0f && ms < bestr) {
           bestr = ms;
@@ -560,7 +578,9 @@ static Pick choose(ils_plan* plan, const FrameDesc& d) {
 // The 2N + 1 launches of one frame with the given shapes on stream st;
 // wrap(kind, launch) issues each launch (kind as in ils_profile_end).
 template <class Wrap>
-static hipError_t enqueue_frame(const Pick& pk, const FrameDesc& d, int N, int pen, hipStream_t st, Wrap&& wrap) {
+static hipError_t enqueue_frame(const Pick& pk, const FrameDesc& d0, int N, int pen, int cus, hipStream_t st,
+                                Wrap&& wrap) {
+  const FrameDesc d = banded(cus, pk.rv, d0);
   const WorkList wrow = one_frame(d, row_items(pk.rv, ilsk::ROW_MID, d));
   const WorkList wfin = one_frame(d, row_items(pk.rv, ilsk::ROW_FINAL, d));
   const WorkList wcol = one_frame(d, col_items(pk.cv, d));
@@ -626,7 +646,7 @@ static int run_frame(ils_plan* plan, const FrameDesc& d, int N, int pen = ilsk::
     return record(plan, enqueue_persist(plan, fo, nullptr, nullptr, d, 1, d.C, d.C, N, pen, first, ctl, plan->stream));
   }
   const Pick pk = choose(plan, d);
-  const hipError_t e = enqueue_frame(pk, d, N, pen, plan->stream, [&](int kind, auto&& launch) {
+  const hipError_t e = enqueue_frame(pk, d, N, pen, plan->cus, plan->stream, [&](int kind, auto&& launch) {
     return timed(plan, kind, launch);
   });
   return record(plan, e);
@@ -720,7 +740,10 @@ int ils_plan_create(ils_plan** plan_out, int max_H, int max_W, int max_C, int ma
   }
   {
     hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, plan->device) == hipSuccess) plan->arch = prop.gcnArchName;
+    if (hipGetDeviceProperties(&prop, plan->device) == hipSuccess) {
+      plan->arch = prop.gcnArchName;
+      plan->cus = prop.multiProcessorCount;
+    }
     const size_t colon = plan->arch.find(':');
     if (colon != std::string::npos) plan->arch.resize(colon);
     load_tune_cache(plan);
@@ -1533,7 +1556,8 @@ int ils_smooth_noalloc(const float* f, int H, int W, int C, float lambda, float 
   d.specB = reinterpret_cast<cf*>(spec + (size_t)C * H * d.ldS * sizeof(cf));
   // default tile shapes: no tuning (timing would create events)
   const Pick pk = default_pick(H, W);
-  const hipError_t e = enqueue_frame(pk, d, N, ilsk::PEN_CHARBONNIER, st, [](int, auto&& launch) { return launch(); });
+  const hipError_t e =
+      enqueue_frame(pk, d, N, ilsk::PEN_CHARBONNIER, 0, st, [](int, auto&& launch) { return launch(); });
   return e == hipSuccess ? ILS_OK : ILS_ERR_HIP;
 }
 
@@ -1557,7 +1581,8 @@ int ils_enqueue_pass(ils_plan* plan, int kind, const float* f, float* out, int H
     e = pk.cv->launch(one_frame(d, col_items(pk.cv, d)), plan->stream);
   } else {
     const int mode = kind == 0 ? ilsk::ROW_FIRST_SAME : kind == 1 ? ilsk::ROW_MID : ilsk::ROW_FINAL;
-    e = pk.rv->launch(mode, ilsk::PEN_CHARBONNIER, one_frame(d, row_items(pk.rv, mode, d)), plan->stream);
+    const FrameDesc db = banded(plan->cus, pk.rv, d);
+    e = pk.rv->launch(mode, ilsk::PEN_CHARBONNIER, one_frame(db, row_items(pk.rv, mode, db)), plan->stream);
   }
   return record(plan, e);
 }

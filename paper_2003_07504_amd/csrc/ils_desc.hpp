@@ -53,7 +53,19 @@ struct FrameDesc {
                     // factor 2 the row R2C leaves in its output)
   float boost;      // final pass writes u + boost (f - u) when non-zero
                     // (detail enhancement); 0 writes u
+  int nb_row;       // row bands per channel (0: as many as bands of the
+                    // kernel's full height need); see row_bands
 };
+
+// Bands of the row passes.  A channel's H rows are split into nb bands, band
+// b holding rows [b H / nb, (b + 1) H / nb) (floor or ceil of H / nb rows);
+// nb is the frame's own count, kept within [ceil(H / G), H] so that no band
+// exceeds the G rows a block holds.
+__host__ __device__ inline int row_bands(const FrameDesc& d, int G) {
+  const int lo = (d.H + G - 1) / G;
+  const int nb = d.nb_row > lo ? d.nb_row : lo;
+  return nb < d.H ? nb : d.H;
+}
 
 // ROW_FIRST_SAME is the first pass when u^0 and f are the same image (the
 // data term is then read once, as u^0).

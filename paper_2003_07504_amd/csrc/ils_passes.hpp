@@ -304,8 +304,9 @@ __device__ __forceinline__ void row_body(const FrameDesc& d, int band, int ch, f
   const int H = d.H;
   const int W = 2 * M;
   const int ldS = d.ldS;
-  const int y0 = band * G;
-  const int Gv = imin(G, H - y0);
+  const int nb = row_bands(d, G);
+  const int y0 = band * H / nb;
+  const int Gv = (band + 1) * H / nb - y0;
   const int tid = threadIdx.x;
   const int slot = tid / T;
   const int lane = tid - slot * T;
@@ -521,8 +522,9 @@ __device__ __forceinline__ void row_final_body(const FrameDesc& d, int band, int
   const int H = d.H;
   const int W = 2 * M;
   const int ldS = d.ldS;
-  const int y0 = band * G;
-  const int Gv = imin(G, H - y0);
+  const int nb = row_bands(d, G);
+  const int y0 = band * H / nb;
+  const int Gv = (band + 1) * H / nb - y0;
   const int tid = threadIdx.x;
   const int slot = tid / T;
   const int lane = tid - slot * T;
