@@ -490,19 +490,23 @@ static float time_launches(ils_plan* plan, const std::function<hipError_t()>& la
 static bool frame_generic(int H, int W) { return !find_ops(W / 2) || !find_ops(H); }
 
 // Row bands of a single frame on `cus` compute units with row shape v: the
-// fewest rounds of one block per CU that the shape's full bands need, filled
+// fewest rounds of resident blocks that the shape's full bands need, filled
 // with as many (shorter, balanced) bands as they hold, but bands of at least
 // four rows (or the shape's height, if less).  The blocks of a round then
-// end together instead of the last round running a few blocks alone.  The
+// end together instead of the last round running a few blocks alone.  Two
+// blocks of a shape count as resident on one CU when its LDS allows it and
+// a block has at most four waves (one wave of each per SIMD).  The
 // runtime-length kernels keep their own bands.
 static FrameDesc banded(int cus, const RowVariant* v, FrameDesc d) {
   d.nb_row = 0;
   if (cus <= 0 || frame_generic(d.H, d.W)) return d;
   const int g = v->rows[ilsk::ROW_MID];
   const int lo = (d.H + g - 1) / g;
-  const long long rounds = ((long long)d.C * lo + cus - 1) / cus;
+  const int per_cu = (v->threads + 63) / 64 <= 4 ? ilsk::resident_blocks(v->lds_bytes) : 1;
+  const long long per_round = (long long)cus * per_cu;
+  const long long rounds = ((long long)d.C * lo + per_round - 1) / per_round;
   const int hi = std::max(lo, d.H / std::min(g, 4));
-  d.nb_row = (int)std::max<long long>(lo, std::min<long long>(rounds * cus / d.C, hi));
+  d.nb_row = (int)std::max<long long>(lo, std::min<long long>(rounds * per_round / d.C, hi));
   return d;
 }
 

@@ -105,11 +105,19 @@ struct RowGeom {
   static constexpr int NPOST = (M + 1 + T - 1) / T;  // post-process elements per lane
 };
 
-// Waves per SIMD that the row-pass workgroups resident on a CU (as many as
-// fit its 160 KB of LDS, at most 8 per SIMD) need; each may then use
-// 512 / waves VGPRs.
+// LDS that co-resident workgroups of one kernel may take on a CU in all.  A
+// single workgroup may use the whole 160 KB, but two are placed on one CU
+// only when each takes at most about 77 KB (measured on MI355X: two blocks
+// of 77 280 B run side by side, two of 79 200 B do not).
+constexpr int kLdsCoresident = 154560;
+constexpr int resident_blocks(int lds_bytes) {
+  return lds_bytes * 2 > kLdsCoresident ? 1 : kLdsCoresident / lds_bytes;
+}
+
+// Waves per SIMD that the workgroups resident on a CU (as many as fit its
+// LDS, at most 8 per SIMD) need; each may then use 512 / waves VGPRs.
 constexpr int resident_waves_per_simd(int threads, int lds_bytes) {
-  const int blocks = 163840 / lds_bytes;
+  const int blocks = resident_blocks(lds_bytes);
   const int waves = blocks * ((threads + 63) / 64);
   return (waves + 3) / 4 > 8 ? 8 : (waves + 3) / 4;
 }
@@ -118,8 +126,8 @@ constexpr int row_waves() {
   return resident_waves_per_simd((G + 2) * RowGeom<P, Q>::T, 4 * ((G + 2) * RowGeom<P, Q>::SLOT_F + RowGeom<P, Q>::TAB_F));
 }
 
-// Rows per row-pass workgroup: two workgroups per CU (160 KB of LDS) when
-// that leaves bands of at least four rows, else one.
+// Rows per row-pass workgroup: about half the LDS of a CU when that leaves
+// bands of at least four rows, else all of it.
 template <int P, int Q>
 constexpr int row_band() {
   constexpr int slot = 4 * RowGeom<P, Q>::SLOT_F;
@@ -161,21 +169,12 @@ constexpr bool col_fits(int P, int Q, int S, int tab_f) {
   return 4 * (col_ex_f(P, Q, S) + tab_f) <= 163840 && S * (P > Q ? P : Q) <= 1024;
 }
 
-// Tables of a column length: the twiddles as a P x (Q|1) matrix [k1][j] plus
-// Sy[l] = 4 sin^2(pi l / H) when they fit beside the exchange of the widest
-// tile the plain vector of twiddles allows, else that vector (indices
-// multiplied out, Sy formed from the twiddles).  The choice is per length, so
-// every tile width of a length computes the same bits.
-template <int P, int Q>
-struct ColTables {
-  static constexpr int H = P * Q;
-  static constexpr int MAT_F = 2 * P * (Q | 1) + H;
-  static constexpr int VEC_F = 2 * H;
-  static constexpr int WIDEST = col_fits(P, Q, 16, VEC_F) ? 16 : col_fits(P, Q, 8, VEC_F) ? 8 : 4;
-  static constexpr bool MAT = col_fits(P, Q, WIDEST, MAT_F);
-  static constexpr int TAB_F = MAT ? MAT_F : VEC_F;
-};
-
+// Tables of a column length: the twiddles as a P x (Q|1) matrix [k1][j]
+// and Sy[l] = 4 sin^2(pi l / H).  A tile copies them into its LDS beside the
+// exchange when that costs no resident block on a CU; otherwise (the tiles
+// of the longest columns) it reads them from global memory, where every
+// block of the length finds them in the cache.  Either way every tile width
+// of a length computes the same bits.
 template <int P, int Q, int S>
 struct ColGeom {
   static constexpr int H = P * Q;
@@ -183,10 +182,11 @@ struct ColGeom {
   static constexpr int QT = Q | 1;  // row stride of the twiddle matrix
   static constexpr int KS = col_ks(Q, S);
   static constexpr int EX_F = col_ex_f(P, Q, S);
-  static constexpr bool MAT = ColTables<P, Q>::MAT;
-  static constexpr int TAB_F = ColTables<P, Q>::TAB_F;
-  static constexpr int LDS_F = EX_F + TAB_F;
-  static constexpr bool fits = col_fits(P, Q, S, TAB_F);
+  static constexpr int TAB_F = 2 * P * QT + H;
+  static constexpr bool fits = col_fits(P, Q, S, 0);
+  static constexpr bool TAB_LDS =
+      col_fits(P, Q, S, TAB_F) && resident_blocks(4 * (EX_F + TAB_F)) == resident_blocks(4 * EX_F);
+  static constexpr int LDS_F = EX_F + (TAB_LDS ? TAB_F : 0);
 };
 
 // Default column tile: the widest whose exchange and table fit the 160 KB of
@@ -565,10 +565,8 @@ __device__ __forceinline__ void row_final_body(const FrameDesc& d, int band, int
 
 // --------------------------------------------------------------------------
 // Column pass.  Block = S columns x T lanes, lane id = s + S * j.
-// LDS: exchange (P x KS complex), twiddles (H complex).  The column
-// eigenvalue 4 sin^2(pi l / H) = (1 - cos t)^2 + sin^2 t, t = 2 pi l / H, is
-// formed from the twiddle table (the squared term keeps full relative
-// precision at small l, where the other is negligible).
+// LDS: exchange (P x KS complex), then the tables (twiddle matrix [k1][j],
+// row stride Q|1, and Sy[l]) when they are kept in LDS.
 // --------------------------------------------------------------------------
 template <int P, int Q, int S_>
 __device__ __forceinline__ void col_body(const FrameDesc& d, int tile, int ch, float* smem) {
@@ -585,8 +583,22 @@ __device__ __forceinline__ void col_body(const FrameDesc& d, int tile, int ch, f
   const ILS_G cf* in = gm(d.specA) + (size_t)ch * H * ldS + cc;
   ILS_G cf* out = gm(d.specB) + (size_t)ch * H * ldS + cc;
   cf* ex = reinterpret_cast<cf*>(smem);
-  cf* tws = reinterpret_cast<cf*>(smem + Geo::EX_F);  // matrix [k1][j] (row stride QT) or vector [l]
-  float* syl = smem + Geo::EX_F + 2 * P * QT;          // Sy[l] (matrix layout only)
+  cf* tws = reinterpret_cast<cf*>(smem + Geo::EX_F);  // LDS copy of the twiddle matrix
+  float* syl = smem + Geo::EX_F + 2 * P * QT;          // LDS copy of Sy
+  const ILS_G cf* gtw = gm(d.twm_col);
+  const ILS_G float* gsy = gm(d.sy);
+  auto tw = [&](int i) -> cf {
+    if constexpr (Geo::TAB_LDS)
+      return tws[i];
+    else
+      return cf(gtw[i]);
+  };
+  auto sy_at = [&](int l) -> float {
+    if constexpr (Geo::TAB_LDS)
+      return syl[l];
+    else
+      return gsy[l];
+  };
 
   cf x[P];
   if (j < Q) {  // stage A loads first: lane n2 = j, rows Q n1 + n2
@@ -596,18 +608,16 @@ __device__ __forceinline__ void col_body(const FrameDesc& d, int tile, int ch, f
     });
   }
   const float sxk = gm(d.sx)[cc];
-  if constexpr (Geo::MAT) {
-    for (int i = tid; i < P * QT; i += blockDim.x) tws[i] = gm(d.twm_col)[i];
-    for (int i = tid; i < H; i += blockDim.x) syl[i] = gm(d.sy)[i];
-  } else {
-    for (int i = tid; i < H; i += blockDim.x) tws[i] = gm(d.tw_col)[i];
+  if constexpr (Geo::TAB_LDS) {
+    for (int i = tid; i < P * QT; i += blockDim.x) tws[i] = gtw[i];
+    for (int i = tid; i < H; i += blockDim.x) syl[i] = gsy[i];
+    __syncthreads();
   }
-  __syncthreads();
   if (j < Q) {
     cf w[P];
     static_for<P>([&](auto k1c) {
       constexpr int k1 = decltype(k1c)::value;
-      if constexpr (k1 > 0) w[k1] = Geo::MAT ? tws[k1 * QT + j] : tws[j * k1];
+      if constexpr (k1 > 0) w[k1] = tw(k1 * QT + j);
     });
     dft<P, -1>(x);
     static_for<P>([&](auto k1c) {
@@ -627,29 +637,40 @@ __device__ __forceinline__ void col_body(const FrameDesc& d, int tile, int ch, f
     const float ksx = fmaf(kappa, sxk, 1.0f);
     static_for<Q>([&](auto k2c) {
       constexpr int k2 = decltype(k2c)::value;
-      float sy;
-      if constexpr (Geo::MAT) {
-        sy = syl[j + P * k2];
-      } else {
-        const cf w = tws[j + P * k2];
-        const float omc = 1.0f - w.x;
-        sy = fmaf(omc, omc, w.y * w.y);
-      }
-      const float den = fmaf(kappa, sy, ksx);
+      const float den = fmaf(kappa, sy_at(j + P * k2), ksx);
       y[k2] = cscale(y[k2], scale * __builtin_amdgcn_rcpf(den));
     });
     dft<Q, +1>(y);
+    // the inverse twiddle of element (k1, n2) (none for n2 = 0): here from
+    // the LDS table, else in stage B', where lanes of one k1 read the global
+    // table coalesced (the same products either way)
     static_for<Q>([&](auto n2c) {
       constexpr int n2 = decltype(n2c)::value;
-      ex[j * KS + n2 * S + s] = (n2 == 0) ? y[n2] : cmulc(y[n2], Geo::MAT ? tws[j * QT + n2] : tws[n2 * j]);
+      if constexpr (Geo::TAB_LDS)
+        ex[j * KS + n2 * S + s] = (n2 == 0) ? y[n2] : cmulc(y[n2], tws[j * QT + n2]);
+      else
+        ex[j * KS + n2 * S + s] = y[n2];
     });
   }
   __syncthreads();
   if (j < Q) {  // stage B': lane n2 = j, P-point inverse over k1
-    static_for<P>([&](auto k1c) {
-      constexpr int k1 = decltype(k1c)::value;
-      x[k1] = ex[k1 * KS + j * S + s];
-    });
+    if constexpr (Geo::TAB_LDS) {
+      static_for<P>([&](auto k1c) {
+        constexpr int k1 = decltype(k1c)::value;
+        x[k1] = ex[k1 * KS + j * S + s];
+      });
+    } else {
+      cf w[P];
+      static_for<P>([&](auto k1c) {
+        constexpr int k1 = decltype(k1c)::value;
+        w[k1] = cf(gtw[k1 * QT + j]);
+      });
+      static_for<P>([&](auto k1c) {
+        constexpr int k1 = decltype(k1c)::value;
+        x[k1] = ex[k1 * KS + j * S + s];
+        if (j != 0) x[k1] = cmulc(x[k1], w[k1]);
+      });
+    }
     dft<P, +1>(x);
     if (col_ok) {
       static_for<P>([&](auto n1c) {
