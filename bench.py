@@ -476,6 +476,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the hot-frame, batched and surrogate figures")
     ap.add_argument("--copy-ref", action="store_true",
                     help="also run one 512 MiB device-to-device copy (reference for HBM byte counters)")
+    ap.add_argument("--small", action="store_true",
+                    help="the 256x256 grey workload (40 Voronoi cells) in place of 1080p RGB, for profiling; "
+                         "implies --no-extras and --no-cpu-baseline")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2003_07504_amd", "weights", "surrogate.npz"))
     args = ap.parse_args()
     if args.gpus != 1:
@@ -493,11 +496,15 @@ def main():
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
     H, W, C, lam, p, eps, N = 1080, 1920, 3, 1.0, 0.8, 1e-4, 4
+    cells = 400
+    if args.small:
+        H, W, C, cells = 256, 256, 1, 40
+        args.no_extras = args.no_cpu_baseline = True
     say(f"generating {args.ring} frames {W}x{H}x{C}")
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     s1 = torch.cuda.Stream(device=dev)  # second stream of the two-stream figure, first of the process
-    frames_np = [voronoi_image(H, W, C, 400, 0.05, seed=1 + i) for i in range(args.ring)]
+    frames_np = [voronoi_image(H, W, C, cells, 0.05, seed=1 + i) for i in range(args.ring)]
     ring = [torch.from_numpy(f).to(dev) for f in frames_np]
     outs = [torch.empty_like(f) for f in ring]
     plan = ils.Plan(H, W, C, max_frames=8)
@@ -645,11 +652,12 @@ def main():
         "ms_per_step": round(ms_per_step, 5),
         "higher_is_better": True,
         "scaling": "weak",
-        "vs_baseline": round(mpx / PAPER_1080P_RGB_MPX_S, 2),
+        "vs_baseline": round(mpx / PAPER_1080P_RGB_MPX_S, 2) if (H, W, C) == (1080, 1920, 3) else None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "ILS 1920x1080 RGB float32, N=4, lambda=1, p=0.8, eps=1e-4, "
-                               f"one frame per step from a ring of {args.ring} distinct Voronoi+Gaussian frames",
+        "config": {"workload": f"ILS {W}x{H} {'RGB' if C == 3 else 'grey'} float32, N=4, lambda=1, p=0.8, "
+                               f"eps=1e-4, one frame per step from a ring of {args.ring} distinct Voronoi+Gaussian "
+                               "frames",
                    "H": H, "W": W, "C": C, "N": N, "lambda": lam, "p": p, "eps": eps,
                    "global_batch": 1, "parallelism": "none (1 GPU)"},
         "fps": round(fps, 1),

@@ -50,6 +50,39 @@ def trace(db):
     return out
 
 
+def timeline(db, chosen, npass):
+    """Whole steps in the trace: runs of the chosen pass kernels from a first
+    row pass to a final row pass, npass launches long.  Returns the medians
+    of (span from the first start to the last end, sum of kernel durations,
+    sum of the gaps between consecutive launches) in microseconds, and the
+    number of steps found."""
+    con = sqlite3.connect(db)
+    rows = con.execute("select name, start, end from kernels order by start").fetchall()
+    names = {v[0]: k for k, v in chosen.items()}
+    steps, cur = [], []
+    for n, st, en in rows:
+        k = names.get(n)
+        if k is None:
+            continue
+        if k == "row_first":
+            cur = [(st, en)]
+        elif cur:
+            cur.append((st, en))
+            if k == "row_final":
+                if len(cur) == npass:
+                    steps.append(cur)
+                cur = []
+    if not steps:
+        return None
+    def med(v):
+        v = sorted(v)
+        return v[len(v) // 2] / 1e3
+    span = med([s[-1][1] - s[0][0] for s in steps])
+    busy = med([sum(e - b for b, e in s) for s in steps])
+    gaps = med([sum(max(0, s[i + 1][0] - s[i][1]) for i in range(len(s) - 1)) for s in steps])
+    return span, busy, gaps, len(steps)
+
+
 def counters(db, largest=False):
     """{kernel name: {counter: average value per dispatch}}, or the largest
     value of any dispatch when largest is set."""
@@ -92,6 +125,7 @@ def main():
     ap.add_argument("--write", required=True)
     ap.add_argument("--sq", default=None)
     ap.add_argument("--size", required=True, help="HxWxC of the profiled workload")
+    ap.add_argument("--iters", type=int, default=4, help="N of the profiled workload")
     ap.add_argument("--command", required=True, help="the rocprofv3 command line that produced the data")
     ap.add_argument("--out", required=True)
     ap.add_argument("--traffic", default=os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
@@ -107,7 +141,7 @@ def main():
     img = C * H * W * 4
     spec = C * H * (W // 2 + 1) * 8
     alg = {"row_first": img + spec, "row_mid": img + 2 * spec, "row_final": img + spec, "column": 2 * spec}
-    lines = [f"# rocprofv3 summary: ILS passes, {W}x{H}x{C} float32, N=4", "",
+    lines = [f"# rocprofv3 summary: ILS passes, {W}x{H}x{C} float32, N={a.iters}", "",
              f"command: {a.command}", f"kernel source hash: {source_hash()}",
              f"counter scale from a {COPY_BYTES >> 20} MiB copy: FETCH_SIZE x{fscale:.4f}, WRITE_SIZE x{wscale:.4f}",
              "", f"{'pass':10s} {'calls':>5s} {'avg_us':>8s} {'min_us':>8s} {'max_us':>8s} "
@@ -126,6 +160,12 @@ def main():
                      f"{rd / 1e6:8.2f} {wb / 1e6:8.2f} {alg[k] / (avg * 1e3):9.1f} {(rd + wb) / (avg * 1e3):9.1f}")
         traffic[f"{k}@{a.size}"] = {"bytes_per_launch": int(rd + wb), "read_bytes": int(rd), "write_bytes": int(wb),
                                     "source_hash": source_hash(), "kernel": name}
+    tl = timeline(a.trace, kt, 2 * a.iters + 1)
+    if tl:
+        span, busy, gaps, n = tl
+        lines += ["", f"steps in the trace: {n} whole sequences of {2 * a.iters + 1} launches; per step (medians): "
+                      f"first start to last end {span:.2f} us, kernel durations {busy:.2f} us, "
+                      f"gaps between launches {gaps:.2f} us"]
     if sq:
         lines += ["", "SQ counters per launch (SQ_INSTS_* and SQ_WAVES per dispatch; cycles summed over SQs):"]
         for k in ("row_first", "row_mid", "column", "row_final"):
