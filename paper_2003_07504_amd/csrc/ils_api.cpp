@@ -1276,6 +1276,8 @@ int ils_smooth_batch(ils_plan* plan, const ils_frame* frames, int n) {
   std::vector<size_t> offs;  // (desc, row starts, fin starts, col starts) per class
   std::vector<long long> chs_offs;  // channel prefix sums of a persistent part with mixed channel counts, or -1
   size_t ctl_used = 0;  // ints of the persistent control area taken
+  int nbig = 0;
+  for (const Class& cl : classes) nbig += cl.big ? 1 : 0;
   for (const Class& cl : classes) {
     Launch L;
     // shapes are tuned for the class's whole work (all channels of all its
@@ -1288,6 +1290,12 @@ int ils_smooth_batch(ils_plan* plan, const ils_frame* frames, int n) {
     tdesc.specA = reinterpret_cast<cf*>(base);
     tdesc.specB = reinterpret_cast<cf*>(base + (size_t)ctot * tdesc.H * tdesc.ldS * sizeof(cf));
     L.pk = choose(plan, tdesc);
+    // A per-frame part runs beside the other chain's parts, where the tuner's
+    // timing of one launch on an idle chip does not carry over to the column
+    // tile: it takes the widest (measured on 32 frames of 4K RGB, N = 10: the
+    // four-column tile, fastest alone because two share a CU, made the batch
+    // 6 % slower than the eight-column one).
+    if (cl.big && nbig >= 2 && !frame_generic(tdesc.H, tdesc.W)) L.pk.cv = &find_ops(tdesc.H)->col[0];
     L.lane = cl.lane;
     L.big = cl.big;
     L.N = cl.N;
