@@ -1505,6 +1505,7 @@ constexpr int kNoAllocDevices = 64;
 struct NoAllocDevice {
   bool ready;
   char* base;  // device address of `scratch` on this device
+  int cus;     // compute units (row banding)
   std::map<int, LenTables> tab;
 };
 NoAllocDevice g_noalloc[kNoAllocDevices];
@@ -1527,6 +1528,9 @@ int noalloc_device(NoAllocDevice** out) {
     build_tables(host, tab);
     if (host.size() > kNoAllocTableBytes) return ILS_ERR_HIP;
     if (hipMemcpy(ptr, host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess) return ILS_ERR_HIP;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 0;
+    nd.cus = cus;
     nd.base = static_cast<char*>(ptr);
     nd.tab = std::move(tab);
     nd.ready = true;
@@ -1569,7 +1573,7 @@ int ils_smooth_noalloc(const float* f, int H, int W, int C, float lambda, float 
   // default tile shapes: no tuning (timing would create events)
   const Pick pk = default_pick(H, W);
   const hipError_t e =
-      enqueue_frame(pk, d, N, ilsk::PEN_CHARBONNIER, 0, st, [](int, auto&& launch) { return launch(); });
+      enqueue_frame(pk, d, N, ilsk::PEN_CHARBONNIER, nd->cus, st, [](int, auto&& launch) { return launch(); });
   return e == hipSuccess ? ILS_OK : ILS_ERR_HIP;
 }
 
