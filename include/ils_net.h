@@ -85,6 +85,22 @@ int ils_surrogate_infer(ils_net* net, ils_plan* plan, const float* f, const floa
                         const float* lam_host, const float* p_host, float eps, int N, int B, int H, int W,
                         float tau, float* out, float* tv_scratch, float* residual_host, int* fallback_host);
 
+/* The same gate for a list of frames of uneven sizes (a host array of
+ * nframes descriptors, 1 <= nframes <= max_B, each an RGB image within the
+ * network's max_H x max_W): frames[i].f is the input, frames[i].out
+ * receives the network output, replaced by plain ILS with frames[i].N
+ * iterations (frames[i].lambda, p, eps) where the frame's fixed-point
+ * residual exceeds tau.  Each frame needs C = 3, the generalised
+ * Charbonnier penalty and u0 = NULL (or f); anything else is
+ * ILS_ERR_INVALID_ARG and nothing is enqueued.  tv_scratch: device float
+ * array of sum_i 3 H_i W_i values (the frames' T(v) in list order);
+ * residual_host: float[nframes]; fallback_host: int[nframes].  The network
+ * runs frame by frame; T(v) and the fallback are one batched call each when
+ * the plan holds the frames (else frame by frame).  Per frame the results
+ * are bitwise those of ils_surrogate_infer.  Synchronises once, like it. */
+int ils_surrogate_infer_frames(ils_net* net, ils_plan* plan, const ils_frame* frames, int nframes, float tau,
+                               float* tv_scratch, float* residual_host, int* fallback_host);
+
 #ifdef __cplusplus
 }
 #endif

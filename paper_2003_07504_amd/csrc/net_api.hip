@@ -58,6 +58,14 @@ constexpr int kWgradBlocks = 256;
 constexpr int kLossBlocks = 256;
 
 // --------------------------------------------------------- small kernels
+// dst[0] = a, dst[1] = b (a frame's lambda and p for the input maps)
+__global__ void k_set_pair(float* dst, float a, float b) {
+  if (threadIdx.x == 0) {
+    dst[0] = a;
+    dst[1] = b;
+  }
+}
+
 __global__ void __launch_bounds__(256) k_pack_input(const float* f, const float* lam, const float* p, bf16* x0,
                                                    int B, int H, int W) {
   const size_t plane = (size_t)H * W;
@@ -666,6 +674,87 @@ static int surrogate_infer_bound(ils_net* n, ils_plan* plan, const float* f, con
     }
     rc = ILS_OK;
   }
+  return rc;
+}
+
+// Frame-list gate: the network frame by frame (its lambda and p maps from two
+// scalars that a one-thread kernel writes into the workspace, so the host
+// stages nothing), then T(v), the residuals and the fallback over the whole
+// list, as in surrogate_infer_bound.
+static int surrogate_infer_frames_bound(ils_net* n, ils_plan* plan, const ils_frame* frames, int nf, float tau,
+                                        float* tv_scratch, float* residual_host, int* fallback_host) {
+  float* lp = reinterpret_cast<float*>(n->lpart);  // lambda, p of the frame in flight
+  std::vector<ils_frame> tv(nf);
+  std::vector<const float*> pa(nf), pb(nf);
+  std::vector<long long> cnt(nf);
+  size_t off = 0;
+  for (int i = 0; i < nf; ++i) {
+    const ils_frame& fr = frames[i];
+    hipLaunchKernelGGL(k_set_pair, dim3(1), dim3(64), 0, n->stream, lp, fr.lambda, fr.p);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = run_forward(n, fr.f, lp, lp + 1, 1, fr.H, fr.W, fr.out);
+    if (e != hipSuccess) return rec(n, e);
+    const size_t img = (size_t)3 * fr.H * fr.W;
+    tv[i] = ils_frame{fr.f, tv_scratch + off, fr.H, fr.W, 3, fr.lambda, fr.p, fr.eps, 1, fr.out,
+                      ILS_PENALTY_CHARBONNIER, 0.0f};
+    pa[i] = tv_scratch + off;
+    pb[i] = fr.out;
+    cnt[i] = (long long)img;
+    off += img;
+  }
+  int rc = ils_smooth_batch(plan, tv.data(), nf);
+  if (rc == ILS_ERR_WORKSPACE || rc == ILS_ERR_INVALID_ARG) {
+    for (const ils_frame& t : tv) {
+      rc = ils_iterate_from(plan, t.f, t.u0, t.H, t.W, 3, t.lambda, t.p, t.eps, 1, t.out);
+      if (rc != ILS_OK) return rc;
+    }
+  }
+  if (rc != ILS_OK) return rc;
+  float* rms_dev = reinterpret_cast<float*>(n->lpart);
+  rc = ils_rms_diff(plan, pa.data(), pb.data(), cnt.data(), nf, rms_dev);
+  if (rc != ILS_OK) return rc;
+  hipError_t e = hipMemcpyAsync(residual_host, rms_dev, nf * sizeof(float), hipMemcpyDeviceToHost, n->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(n->stream);
+  if (e != hipSuccess) return rec(n, e);
+  std::vector<ils_frame> fb;
+  for (int i = 0; i < nf; ++i) {
+    fallback_host[i] = !(residual_host[i] <= tau);  // NaN residual also falls back
+    if (fallback_host[i]) {
+      const ils_frame& fr = frames[i];
+      fb.push_back(ils_frame{fr.f, fr.out, fr.H, fr.W, 3, fr.lambda, fr.p, fr.eps, fr.N, nullptr,
+                             ILS_PENALTY_CHARBONNIER, 0.0f});
+    }
+  }
+  if (fb.empty()) return ILS_OK;
+  rc = ils_smooth_batch(plan, fb.data(), (int)fb.size());
+  if (rc == ILS_ERR_WORKSPACE || rc == ILS_ERR_INVALID_ARG) {
+    for (const ils_frame& fr : fb) {
+      rc = ils_smooth(plan, fr.f, fr.H, fr.W, 3, fr.lambda, fr.p, fr.eps, fr.N, fr.out);
+      if (rc != ILS_OK) return rc;
+    }
+    rc = ILS_OK;
+  }
+  return rc;
+}
+
+int ils_surrogate_infer_frames(ils_net* n, ils_plan* plan, const ils_frame* frames, int nframes, float tau,
+                               float* tv_scratch, float* residual_host, int* fallback_host) {
+  if (!n || !plan || !frames || !tv_scratch || !residual_host || !fallback_host) return ILS_ERR_INVALID_ARG;
+  if (nframes < 1 || nframes > n->max_B) return ILS_ERR_INVALID_ARG;
+  if (!std::isfinite(tau)) return ILS_ERR_NOT_CALIBRATED;
+  for (int i = 0; i < nframes; ++i) {
+    const ils_frame& fr = frames[i];
+    if (!fr.f || !fr.out || fr.C != 3 || fr.penalty != ILS_PENALTY_CHARBONNIER || (fr.u0 && fr.u0 != fr.f))
+      return ILS_ERR_INVALID_ARG;
+    int rc = check_batch(n, 1, fr.H, fr.W);
+    if (rc == ILS_OK) rc = ils_check_args(fr.H, fr.W, 3, fr.lambda, fr.p, fr.eps, fr.N);
+    if (rc != ILS_OK) return rc;
+  }
+  void* saved = ilsk_plan_stream(plan);
+  int rc = ils_plan_set_stream(plan, n->stream);
+  if (rc != ILS_OK) return rc;
+  rc = surrogate_infer_frames_bound(n, plan, frames, nframes, tau, tv_scratch, residual_host, fallback_host);
+  (void)ils_plan_set_stream(plan, saved);
   return rc;
 }
 

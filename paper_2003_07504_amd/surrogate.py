@@ -37,6 +37,8 @@ _SIGS = {
     "ils_surrogate_infer": (ctypes.c_int, [ctypes.c_void_p] * 7 + [ctypes.c_float, ctypes.c_int, ctypes.c_int,
                                                                     ctypes.c_int, ctypes.c_int, ctypes.c_float]
                             + [ctypes.c_void_p] * 4),
+    "ils_surrogate_infer_frames": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                                  ctypes.c_float, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
 }
 
 
@@ -210,8 +212,8 @@ class Net:
         fallback where the fixed-point residual exceeds tau."""
         f = _img(f, "f")
         B, _, H, W = f.shape
-        lam_h = np.ascontiguousarray(np.broadcast_to(np.asarray(lam, dtype=np.float32), (B,)))
-        p_h = np.ascontiguousarray(np.broadcast_to(np.asarray(p, dtype=np.float32), (B,)))
+        lam_h = np.array(np.broadcast_to(np.asarray(lam, dtype=np.float32), (B,)))
+        p_h = np.array(np.broadcast_to(np.asarray(p, dtype=np.float32), (B,)))
         lam_t = torch.as_tensor(lam_h, device=self.device)
         p_t = torch.as_tensor(p_h, device=self.device)
         out = torch.empty_like(f) if out is None else _img(out, "out")
@@ -224,6 +226,30 @@ class Net:
                                             float(tau), out.data_ptr(), scratch.data_ptr(), res.ctypes.data,
                                             fb.ctypes.data), "ils_surrogate_infer")
         return out, res, fb.astype(bool)
+
+    def infer_gated_frames(self, plan, frames, tau: float, outs=None):
+        """The gate over a list of (f, lam, p, eps, N) RGB frames of any sizes
+        within the network's limits, f of shape (3, H, W): (outs, residual[n],
+        fallback[n])."""
+        from ._lib import IlsFrame, PENALTY_CHARBONNIER
+        n = len(frames)
+        fs = [f.contiguous() for f, *_ in frames]
+        for f in fs:
+            if f.dim() != 3 or f.shape[0] != 3 or f.dtype != torch.float32 or f.device != self.device:
+                raise ValueError("frames must be (3, H, W) float32 tensors on the network's device")
+        outs = [torch.empty_like(f) for f in fs] if outs is None else list(outs)
+        arr = (IlsFrame * n)()
+        for i, ((_, lam, p, eps, N), f, o) in enumerate(zip(frames, fs, outs)):
+            arr[i] = IlsFrame(f.data_ptr(), o.data_ptr(), f.shape[1], f.shape[2], 3, float(lam), float(p),
+                              float(eps), int(N), None, PENALTY_CHARBONNIER, 0.0)
+        scratch = torch.empty(sum(f.numel() for f in fs), dtype=torch.float32, device=self.device)
+        res = np.empty(n, dtype=np.float32)
+        fb = np.empty(n, dtype=np.int32)
+        self._bind()
+        check(self._lib.ils_surrogate_infer_frames(self._h, plan._h, ctypes.addressof(arr), n, float(tau),
+                                                   scratch.data_ptr(), res.ctypes.data, fb.ctypes.data),
+              "ils_surrogate_infer_frames")
+        return outs, res, fb.astype(bool)
 
 
 def _main():

@@ -227,3 +227,46 @@ def test_gate_tau_extremes(torch, S, max_frames):
         net.infer_gated(plan, ft, lam, p, 1e-4, 4, float("inf"))
     net.close()
     plan.close()
+
+
+# max_frames = 1: T(v) and the fallback frame by frame; 5: one batched call each
+@pytest.mark.parametrize("max_frames", [1, 5])
+def test_gate_frame_list_matches_same_size_gate(torch, S, max_frames):
+    """The frame-list gate over frames of two sizes gives, frame by frame,
+    the bits of the same-size gate (network output, residual, fallback
+    choice, plain-ILS fallback), with tau between the residuals so that both
+    outcomes occur; malformed lists are refused."""
+    _say(f"gate over a frame list of two sizes, plan of {max_frames} frame(s)")
+    from paper_2003_07504_amd import ils
+    from paper_2003_07504_amd._lib import IlsError
+    sizes = [(32, 64), (48, 40), (32, 64), (48, 40), (32, 64)]
+    rng = np.random.default_rng(21)
+    frames = []
+    for i, (H, W) in enumerate(sizes):
+        f = voronoi_image(H, W, 3, 6, 0.05, seed=300 + i).astype(np.float32)
+        frames.append((torch.from_numpy(f).cuda(), float(rng.uniform(0.5, 2.0)), float(rng.uniform(0.5, 1.0)),
+                       1e-4, 4))
+    plan = ils.Plan(48, 64, 3, max_frames=max_frames)
+    net = S.Net(len(sizes), 48, 64, seed=3)
+    # residuals first (tau huge: no fallback), then tau between them
+    _, r_all, fb_all = net.infer_gated_frames(plan, frames, 1e30)
+    torch.cuda.synchronize()
+    assert not fb_all.any() and np.all(np.isfinite(r_all)) and np.all(r_all > 0)
+    tau = float(np.median(r_all))
+    outs, res, fb = net.infer_gated_frames(plan, frames, tau)
+    torch.cuda.synchronize()
+    assert fb.any() and not fb.all()
+    assert np.array_equal(res, r_all)
+    for i, (f, lam, p, eps, N) in enumerate(frames):
+        o1, r1, fb1 = net.infer_gated(plan, f[None], np.float32(lam), np.float32(p), eps, N, tau)
+        torch.cuda.synchronize()
+        assert torch.equal(o1[0], outs[i]), i
+        assert r1[0] == res[i] and bool(fb1[0]) == bool(fb[i]), i
+    # refused: a grey frame, more frames than the network holds
+    grey = (frames[0][0][:1].contiguous(),) + frames[0][1:]
+    with pytest.raises(ValueError):
+        net.infer_gated_frames(plan, [grey], tau)
+    with pytest.raises(IlsError):
+        net.infer_gated_frames(plan, frames + frames[:1], tau)
+    net.close()
+    plan.close()
