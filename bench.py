@@ -479,6 +479,10 @@ def main():
     ap.add_argument("--small", action="store_true",
                     help="the 256x256 grey workload (40 Voronoi cells) in place of 1080p RGB, for profiling; "
                          "implies --no-extras and --no-cpu-baseline")
+    ap.add_argument("--stress", action="store_true",
+                    help="single 3840x2160 RGB frames of the stress workload (2000 cells, sigma 0.08, lambda 2, "
+                         "p 0.5, N 10; ring of 8) in place of 1080p RGB, for profiling; implies --no-extras and "
+                         "--no-cpu-baseline")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2003_07504_amd", "weights", "surrogate.npz"))
     args = ap.parse_args()
     if args.gpus != 1:
@@ -496,15 +500,19 @@ def main():
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
     H, W, C, lam, p, eps, N = 1080, 1920, 3, 1.0, 0.8, 1e-4, 4
-    cells = 400
+    cells, sigma = 400, 0.05
     if args.small:
         H, W, C, cells = 256, 256, 1, 40
+        args.no_extras = args.no_cpu_baseline = True
+    if args.stress:
+        H, W, C, lam, p, N, cells, sigma = 2160, 3840, 3, 2.0, 0.5, 10, 2000, 0.08
+        args.ring = min(args.ring, 8)
         args.no_extras = args.no_cpu_baseline = True
     say(f"generating {args.ring} frames {W}x{H}x{C}")
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     s1 = torch.cuda.Stream(device=dev)  # second stream of the two-stream figure, first of the process
-    frames_np = [voronoi_image(H, W, C, cells, 0.05, seed=1 + i) for i in range(args.ring)]
+    frames_np = [voronoi_image(H, W, C, cells, sigma, seed=1 + i) for i in range(args.ring)]
     ring = [torch.from_numpy(f).to(dev) for f in frames_np]
     outs = [torch.empty_like(f) for f in ring]
     plan = ils.Plan(H, W, C, max_frames=8)
@@ -655,9 +663,9 @@ def main():
         "vs_baseline": round(mpx / PAPER_1080P_RGB_MPX_S, 2) if (H, W, C) == (1080, 1920, 3) else None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"ILS {W}x{H} {'RGB' if C == 3 else 'grey'} float32, N=4, lambda=1, p=0.8, "
-                               f"eps=1e-4, one frame per step from a ring of {args.ring} distinct Voronoi+Gaussian "
-                               "frames",
+        "config": {"workload": f"ILS {W}x{H} {'RGB' if C == 3 else 'grey'} float32, N={N}, lambda={lam:g}, "
+                               f"p={p:g}, eps=1e-4, one frame per step from a ring of {args.ring} distinct "
+                               "Voronoi+Gaussian frames",
                    "H": H, "W": W, "C": C, "N": N, "lambda": lam, "p": p, "eps": eps,
                    "global_batch": 1, "parallelism": "none (1 GPU)"},
         "fps": round(fps, 1),
