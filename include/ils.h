@@ -286,7 +286,11 @@ int ils_last_error(ils_plan* plan);
  * times the shapes on the plan's stream (a few launches on workspace data,
  * one host synchronisation) and keeps the faster ones for the plan's life.
  * A call made while the stream is being captured into a graph keeps the
- * default shapes and leaves the size untuned.  Environment: ILS_TUNE=0
+ * default shapes and leaves the size untuned.  A row shape's height is the
+ * most rows a workgroup holds: a single frame's rows are cut into balanced
+ * bands of at most that many rows, as many as fill whole rounds of the
+ * compute units.  In ils_smooth_batch, frames large enough to be parts of
+ * their own take the widest column tile.  Environment: ILS_TUNE=0
  * keeps the defaults; ILS_TUNE_CACHE=<file> reads earlier choices at plan
  * creation ("arch H W C rows-per-band columns-per-tile" per line) and
  * appends new ones.
