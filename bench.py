@@ -486,7 +486,7 @@ def main():
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2003_07504_amd", "weights", "surrogate.npz"))
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: --gpus {args.gpus} is not supported: this build runs on one GPU only "
+        print(f"bench.py: --gpus {args.gpus} is not supported: the library runs on one GPU only "
               "(frames would shard across GPUs with no exchange; see the design notes).", file=sys.stderr)
         sys.exit(2)
 

@@ -116,7 +116,7 @@ size_t ils_batch_workspace_bytes(const ils_frame* frames, int n);
 int ils_plan_create(ils_plan** plan, int max_H, int max_W, int max_C, int max_frames,
                     void* workspace, size_t ws_bytes, void* hip_stream, unsigned flags);
 
-/* Persistent single-launch sequences (SWITCHED OFF in this build).  The
+/* Persistent single-launch sequences (SWITCHED OFF in this library).  The
  * design: for the sizes compiled with one (256 x 256, 640 x 480,
  * 1280 x 720, 1920 x 1080, 3840 x 2160), ils_smooth and the batched calls
  * would run the 2N + 1 passes of a frame (or of a part of a batch) in one
